@@ -1,0 +1,101 @@
+"""Pins for the reading of the truncated reduction (Section 5, Theorems 1-2).
+
+Every variant of oracle/montred_model.py is compared with the exact
+Montgomery integer (T + qN)/R, the value Algorithm 5 returns, exhaustively
+over small limb widths and randomly at the library's limb width.
+"""
+import random
+
+import pytest
+
+import oracle
+from oracle import montred_model as m
+
+SMALL = [(2, 2), (3, 2), (4, 2), (3, 3), (4, 3), (3, 4)]
+
+
+def _cases(L, n, cap=None):
+    """Every odd N <= R/4 and evenly spaced T < 4N^2 (all T when few enough), plus T = 4N^2 - 1."""
+    R = 1 << (L * n)
+    mods = range(3, R // 4 + 1, 2)
+    if cap is None:
+        cap = max(64, 60000 // len(mods))
+    for N in mods:
+        lim = 4 * N * N
+        step = max(1, lim // cap)
+        for T in range(0, lim, step):
+            yield N, T
+        yield N, lim - 1
+
+
+@pytest.mark.parametrize("L,n", SMALL)
+def test_theorem1_and_ceil_reading_exhaustive(L, n):
+    for N, T in _cases(L, n):
+        e = m.redc_exact(T, N, L, n)
+        assert m.theorem1_form(T, N, L, n) == e
+        if 2 * n - 3 < (1 << L):
+            assert m.redc_truncated(T, N, L, n, "floor") == e
+        if n - 1 < (1 << (L - 1)):
+            assert m.redc_truncated(T, N, L, n, "nearest") == e
+        if m.fullcol_condition(L, n):
+            assert m.redc_truncated_fullcol(T, N, L, n) == e
+
+
+def test_ceil_reading_needs_its_condition():
+    """At L=2, n=4 the unknown carry reaches 2^L and the ceil reading must fail somewhere."""
+    L, n = 2, 4
+    bad = sum(m.redc_truncated(T, N, L, n) != m.redc_exact(T, N, L, n) for N, T in _cases(L, n, 400))
+    assert bad > 0
+
+
+def test_literal_reading_disagrees_with_exact_redc():
+    """Feeding c_add in as the carry into column n-1 (equations (3)-(5) read literally) is wrong."""
+    for L, n in SMALL:
+        bad = sum(m.redc_truncated_literal(T, N, L, n) != m.redc_exact(T, N, L, n)
+                  for N, T in _cases(L, n, 300))
+        assert bad > 0, (L, n)
+
+
+def test_fullcol_reading_fails_when_window_too_narrow():
+    rng = random.Random(11)
+    L, n = 1, 8
+    assert not m.fullcol_condition(L, n)
+    R = 1 << (L * n)
+    bad = 0
+    for _ in range(3000):
+        N = rng.randrange(3, R // 4 + 1) | 1
+        if N > R // 4:
+            N -= 2
+        T = rng.randrange(4 * N * N)
+        bad += m.redc_truncated_fullcol(T, N, L, n) != m.redc_exact(T, N, L, n)
+    assert bad > 0
+
+
+@pytest.mark.parametrize("n", [3, 5, 10, 19, 37, 74, 110, 147])
+def test_fullcol_reading_random_at_28bit_limbs(n):
+    rng = random.Random(100 + n)
+    L = 28
+    assert m.fullcol_condition(L, n)
+    R = 1 << (L * n)
+    t = L * n - 2
+    for trial in range(40):
+        N = rng.getrandbits(t) | 1 | (1 << (t - 1))
+        specials = [0, 1, N, 2 * N - 1, (2 * N - 1) ** 2, 1 << t, (1 << t) << L, R - 1, R]
+        T = specials[trial] if trial < len(specials) else rng.randrange(4 * N * N)
+        e = m.redc_exact(T, N, L, n)
+        assert m.redc_truncated_fullcol(T, N, L, n) == e
+        assert e == oracle.redc(T, N, L * n)
+        if T < 4 * N * N:
+            assert e < 2 * N
+
+
+def test_counts_formulas():
+    # products per operation derived from the schedules; n=33 / 65 at 32-bit limbs
+    for n, mul_p, mul_t, sqr_p, sqr_t in ((33, 2739, 2243, 2211, 1715), (65, 10595, 8579, 8515, 6499),
+                                          (129, 41667, 33539, 33411, 25283)):
+        c = m.counts(n)
+        assert (c["mul_plain"], c["mul_trunc"], c["sqr_plain"], c["sqr_trunc"]) == (mul_p, mul_t, sqr_p, sqr_t)
+    # the truncated partial-product set of Theorem 2 has n(n+1)/2 + n - 1 members
+    for n in (2, 3, 7, 33):
+        cnt = sum(1 for i in range(n) for j in range(n) if i + j >= n - 2)
+        assert cnt == n * (n + 1) // 2 + n - 1
