@@ -1,0 +1,113 @@
+/*
+ * montexp.h -- C ABI of libmontexp.so: batched Montgomery modular
+ * multiplication / squaring with truncated reduction and constant-time
+ * fixed-window modular exponentiation on AMD MI355X (gfx950).
+ *
+ * Paper: "Truncated multiplication and batch software SIMD AVX512
+ * implementation for faster Montgomery multiplications and modular
+ * exponentiation" (Didier, El Mrabet, Glandus, Robert).
+ *
+ * Conventions for every entry point:
+ *  - Multiprecision values are little-endian arrays of uint64_t words (the
+ *    GMP mpn order the paper's exponentiation takes, Section 6, Algorithm 7).
+ *    Instance i of a batch starts at ptr + i * words.
+ *  - Operand pointers are DEVICE pointers unless the name says _host.
+ *    `stream` is a hipStream_t (NULL = the default stream).  Batch calls
+ *    only enqueue work: results are valid after the stream synchronises.
+ *  - Size classes: bits in {64, 128, 256, 512, 1024, 2048}.  A class uses
+ *    n = ceil((bits + 2) / 28) limbs of 28 bits and R = 2^(28 n) >= 4 * 2^bits
+ *    (r_bits = 28 n, reported by mont_ctx_query), so products of values below
+ *    2N reduce to values below 2N with no final subtraction (Section 4).
+ *  - Canonical values (< N) use words = ceil(bits / 64); Montgomery-domain
+ *    values (< 2N) use mont_words = ceil(r_bits / 64).
+ *  - The caller owns all operand buffers and the stream; the library owns
+ *    context memory and its exponentiation workspace.
+ *  - Errors: host-checkable arguments give MX_EINVAL synchronously; launch
+ *    or device errors give MX_EDEVICE; mont_last_error() returns a
+ *    thread-local message for the last non-OK status.  No call aborts.
+ *  - Device-data preconditions (a, b < 2N; base < N) are not checked: a
+ *    violation gives an unspecified value, never an out-of-bounds access.
+ *    ctx_idx entries >= the context count are replaced by 0.
+ */
+#ifndef MONTEXP_H
+#define MONTEXP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mont_ctx mont_ctx; /* opaque, device-resident, immutable after init */
+
+typedef enum {
+  MX_OK = 0,
+  MX_EINVAL = 1,
+  MX_ENOMEM = 2,
+  MX_EDEVICE = 3,
+  MX_EUNSUPPORTED = 4
+} mx_status;
+
+/* flags for the batch calls */
+enum {
+  MX_REDC_TRUNC = 0, /* truncated reduction, Section 5 Algorithm 6 (default)  */
+  MX_REDC_PLAIN = 1  /* full q*N product, Section 4 Algorithm 3 (B_fma)        */
+};
+
+/* Montgomery contexts for `count` moduli of size class `bits` (Section 4:
+ * N' = (-N)^{-1} mod R, R^2 mod N for conversion into Montgomery form, and
+ * R mod N, the Montgomery form of 1).  moduli_host: count * ceil(bits/64)
+ * words in host memory; each modulus odd, >= 3 and below 2^bits, else
+ * MX_EINVAL (the offending index is in mont_last_error()).  The constants
+ * are computed on the device; the call blocks until they are resident.
+ * *out receives the context (NULL on failure); free with mont_ctx_destroy. */
+mx_status mont_ctx_init(mont_ctx **out, const uint64_t *moduli_host, uint32_t bits, uint32_t count,
+                        void *stream);
+
+/* Size class, r_bits (log2 R), limb bits (28), context count and device bytes.
+ * Any output pointer may be NULL. */
+mx_status mont_ctx_query(const mont_ctx *ctx, uint32_t *bits, uint32_t *r_bits, uint32_t *limb_bits,
+                         uint32_t *count, size_t *device_bytes);
+
+/* Copies context `idx` to host memory as mont_words words each: N' mod R,
+ * R^2 mod N and R mod N.  Synchronous; any output pointer may be NULL. */
+mx_status mont_ctx_export(const mont_ctx *ctx, uint32_t idx, uint64_t *nprime_host, uint64_t *r2_host,
+                          uint64_t *r1_host);
+
+/* Frees the context.  The caller guarantees no queued work still uses it. */
+void mont_ctx_destroy(mont_ctx *ctx);
+
+/* out[i] = REDC(a[i] * b[i]) = (a b + q N) / R exactly, q = -a b N^{-1} mod R
+ * (Algorithm 5's value; Algorithms 3 and 6 compute it, Theorem 1).  Values
+ * are mont_words wide; precondition a, b < 2N, result < 2N.  MX_REDC_TRUNC
+ * and MX_REDC_PLAIN return identical bits.  ctx_idx (device, n entries) picks
+ * the context of each instance; NULL means instance i uses context i (then
+ * n <= count).  out may alias a or b.  n = 0 is a no-op. */
+mx_status mont_mul_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint64_t *a, const uint64_t *b,
+                         uint64_t *out, uint32_t n, uint32_t flags, void *stream);
+
+/* out[i] = REDC(a[i]^2), as mont_mul_batch with b = a (squaring, Algorithm 2). */
+mx_status mont_sqr_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint64_t *a, uint64_t *out,
+                         uint32_t n, uint32_t flags, void *stream);
+
+/* out[i] = base[i]^exp[i] mod N, canonical in [0, N), by the constant-time
+ * left-to-right fixed-window exponentiation of Algorithm 7 (table of 2^w
+ * Montgomery powers, full masked table scan per window).  base: words wide,
+ * base < N.  exp: ceil(exp_bits / 64) words per instance; exp_bits is public
+ * and leading zeros are processed; bits above exp_bits are ignored.
+ * exp_bits = 0 gives 1 (also 0^0 = 1).  window in 1..8, 0 = library choice.
+ * The library-owned workspace (2^w * r_bits/8 bytes per instance) grows on
+ * demand; a growth allocates device memory.  out may alias base. */
+mx_status modexp_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint64_t *base, const uint64_t *exp,
+                       uint32_t exp_bits, uint32_t window, uint64_t *out, uint32_t n, uint32_t flags,
+                       void *stream);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char *mont_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MONTEXP_H */

@@ -1,0 +1,244 @@
+// C ABI of libmontexp.so (declared in include/montexp.h): argument checks,
+// context ownership, workspace management and kernel launches.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "../../include/montexp.h"
+#include "mx_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+mx_status fail(mx_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+mx_status dev_fail(hipError_t e, const char* where) {
+  return fail(e == hipErrorOutOfMemory ? MX_ENOMEM : MX_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+uint32_t words_for(uint32_t bits) { return (bits + 63) / 64; }
+uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
+
+uint32_t default_window(uint32_t bits) {
+  if (bits <= 128) return 3;
+  if (bits <= 512) return 4;
+  if (bits <= 3072) return 5;
+  return 6;
+}
+
+// Switches to `dev` for the lifetime of the guard when it is not current.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct mont_ctx {
+  const mx::ClassOps* ops = nullptr;
+  uint32_t bits = 0;
+  uint32_t limbs = 0;
+  uint32_t count = 0;
+  int device = 0;
+  mx::CtxDev dev{};
+  void* mem = nullptr;
+  size_t bytes = 0;
+  // exponentiation workspace owned by the context (grow-only)
+  std::mutex ws_mu;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+extern "C" {
+
+const char* mont_last_error(void) { return g_err; }
+
+mx_status mont_ctx_init(mont_ctx** out, const uint64_t* moduli_host, uint32_t bits, uint32_t count, void* stream) {
+  if (!out) return fail(MX_EINVAL, "mont_ctx_init: out is NULL");
+  *out = nullptr;
+  const mx::ClassOps* ops = mx::class_ops(bits);
+  if (!ops) return fail(MX_EINVAL, "mont_ctx_init: unsupported size class %u", bits);
+  const int limbs = ops->limbs;
+  if (!moduli_host) return fail(MX_EINVAL, "mont_ctx_init: moduli_host is NULL");
+  if (count == 0) return fail(MX_EINVAL, "mont_ctx_init: count is 0");
+  const uint32_t W = words_for(bits);
+  const uint32_t topbits = bits - 64 * (W - 1);
+  for (uint32_t k = 0; k < count; ++k) {
+    const uint64_t* m = moduli_host + (size_t)k * W;
+    if ((m[0] & 1u) == 0) return fail(MX_EINVAL, "mont_ctx_init: modulus %u is even", k);
+    bool big = false;
+    for (uint32_t j = 1; j < W; ++j) big |= m[j] != 0;
+    if (!big && m[0] < 3) return fail(MX_EINVAL, "mont_ctx_init: modulus %u is below 3", k);
+    if (topbits < 64 && (m[W - 1] >> topbits) != 0)
+      return fail(MX_EINVAL, "mont_ctx_init: modulus %u exceeds %u bits", k, bits);
+  }
+  mont_ctx* c = new (std::nothrow) mont_ctx;
+  if (!c) return fail(MX_ENOMEM, "mont_ctx_init: host allocation failed");
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(MX_EDEVICE, "mont_ctx_init: no HIP device");
+  }
+  c->ops = ops;
+  c->bits = bits;
+  c->limbs = (uint32_t)limbs;
+  c->count = count;
+  const uint32_t stride = round_up(count, 64);
+  const size_t arr = (size_t)limbs * stride * sizeof(uint32_t);
+  c->bytes = 4 * arr;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMalloc(&c->mem, c->bytes);
+  if (e != hipSuccess) {
+    delete c;
+    return dev_fail(e, "mont_ctx_init: context allocation");
+  }
+  uint8_t* base = (uint8_t*)c->mem;
+  c->dev.n = (uint32_t*)(base);
+  c->dev.np = (uint32_t*)(base + arr);
+  c->dev.r2 = (uint32_t*)(base + 2 * arr);
+  c->dev.r1 = (uint32_t*)(base + 3 * arr);
+  c->dev.count = count;
+  c->dev.stride = stride;
+  uint64_t* dmods = nullptr;
+  const size_t mbytes = (size_t)count * W * sizeof(uint64_t);
+  e = hipMalloc(&dmods, mbytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(dmods, moduli_host, mbytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(c->mem, 0, c->bytes, st);
+  if (e == hipSuccess) e = ops->ctx_init(dmods, c->dev, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (dmods) (void)hipFree(dmods);
+  if (e != hipSuccess) {
+    (void)hipFree(c->mem);
+    delete c;
+    return dev_fail(e, "mont_ctx_init");
+  }
+  *out = c;
+  return MX_OK;
+}
+
+mx_status mont_ctx_query(const mont_ctx* ctx, uint32_t* bits, uint32_t* r_bits, uint32_t* limb_bits,
+                         uint32_t* count, size_t* device_bytes) {
+  if (!ctx) return fail(MX_EINVAL, "mont_ctx_query: ctx is NULL");
+  if (bits) *bits = ctx->bits;
+  if (r_bits) *r_bits = 28 * ctx->limbs;
+  if (limb_bits) *limb_bits = 28;
+  if (count) *count = ctx->count;
+  if (device_bytes) *device_bytes = ctx->bytes + ctx->ws_bytes;
+  return MX_OK;
+}
+
+mx_status mont_ctx_export(const mont_ctx* ctx, uint32_t idx, uint64_t* nprime_host, uint64_t* r2_host,
+                          uint64_t* r1_host) {
+  if (!ctx) return fail(MX_EINVAL, "mont_ctx_export: ctx is NULL");
+  if (idx >= ctx->count) return fail(MX_EINVAL, "mont_ctx_export: index %u >= count %u", idx, ctx->count);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(MX_EDEVICE, "mont_ctx_export: cannot select device");
+  const uint32_t n = ctx->limbs;
+  const uint32_t mw = words_for(28 * n);
+  const uint32_t* srcs[3] = {ctx->dev.np, ctx->dev.r2, ctx->dev.r1};
+  uint64_t* dsts[3] = {nprime_host, r2_host, r1_host};
+  uint32_t limbs[512];
+  for (int a = 0; a < 3; ++a) {
+    if (!dsts[a]) continue;
+    hipError_t e = hipMemcpy2D(limbs, sizeof(uint32_t), srcs[a] + idx, (size_t)ctx->dev.stride * sizeof(uint32_t),
+                               sizeof(uint32_t), n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_fail(e, "mont_ctx_export");
+    memset(dsts[a], 0, mw * sizeof(uint64_t));
+    for (uint32_t i = 0; i < n; ++i) {
+      const uint32_t bit = 28 * i, wd = bit / 64, off = bit % 64;
+      dsts[a][wd] |= (uint64_t)limbs[i] << off;
+      if (off > 36 && wd + 1 < mw) dsts[a][wd + 1] |= (uint64_t)limbs[i] >> (64 - off);
+    }
+  }
+  return MX_OK;
+}
+
+void mont_ctx_destroy(mont_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->mem) (void)hipFree(ctx->mem);
+  delete ctx;
+}
+
+static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* a,
+                             const uint64_t* b, uint64_t* out, uint32_t n, uint32_t flags, void* stream, bool sqr) {
+  if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
+  if (n == 0) return MX_OK;
+  if (!a || !out || (!sqr && !b)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
+  if (flags & ~(uint32_t)MX_REDC_PLAIN) return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
+  if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
+  hipError_t e = ctx->ops->mont(!(flags & MX_REDC_PLAIN), sqr, ctx->dev, ctx_idx, a, b, out, n,
+                                 (hipStream_t)stream);
+  if (e != hipSuccess) return dev_fail(e, name);
+  return MX_OK;
+}
+
+mx_status mont_mul_batch(const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* a, const uint64_t* b,
+                         uint64_t* out, uint32_t n, uint32_t flags, void* stream) {
+  return mont_common("mont_mul_batch", ctx, ctx_idx, a, b, out, n, flags, stream, false);
+}
+
+mx_status mont_sqr_batch(const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* a, uint64_t* out, uint32_t n,
+                         uint32_t flags, void* stream) {
+  return mont_common("mont_sqr_batch", ctx, ctx_idx, a, a, out, n, flags, stream, true);
+}
+
+mx_status modexp_batch(const mont_ctx* cctx, const uint32_t* ctx_idx, const uint64_t* base, const uint64_t* exp,
+                       uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n, uint32_t flags, void* stream) {
+  static const char* name = "modexp_batch";
+  mont_ctx* ctx = const_cast<mont_ctx*>(cctx);
+  if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
+  if (n == 0) return MX_OK;
+  if (!base || !out || (exp_bits && !exp)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
+  if (flags & ~(uint32_t)MX_REDC_PLAIN) return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
+  if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
+  if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
+  const uint32_t w = window ? window : default_window(ctx->bits);
+  const uint32_t ewords = (exp_bits + 63) / 64;
+  const uint32_t tstride = round_up(n, 64);
+  const size_t need = ((size_t)1 << w) * ctx->limbs * tstride * sizeof(uint32_t);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
+  std::lock_guard<std::mutex> lk(ctx->ws_mu);
+  if (ctx->ws_bytes < need) {
+    // the old buffer may still be read by queued work: drain before freeing
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return dev_fail(e, name);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    e = hipMalloc(&ctx->ws, need);
+    if (e != hipSuccess) return dev_fail(e, "modexp_batch: workspace allocation");
+    ctx->ws_bytes = need;
+  }
+  hipError_t e = ctx->ops->modexp(!(flags & MX_REDC_PLAIN), ctx->dev, ctx_idx, base, exp, exp_bits,
+                                   ewords, w, out, n, (uint32_t*)ctx->ws, tstride, (hipStream_t)stream);
+  if (e != hipSuccess) return dev_fail(e, name);
+  return MX_OK;
+}
+
+}  // extern "C"

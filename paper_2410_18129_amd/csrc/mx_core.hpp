@@ -1,0 +1,203 @@
+// Device arithmetic for batched Montgomery multiplication on gfx950.
+//
+// One instance per lane: the word-slicing of Section 2 (Table 1), where every
+// SIMD lane carries one independent instance, mapped onto 64-lane wavefronts.
+// Numbers are little-endian arrays of 28-bit limbs held in 32-bit registers.
+// A 28x28-bit partial product is one v_mad_u64_u32 accumulated into a 64-bit
+// column sum; a column of up to 255 such products cannot overflow, so the
+// products run without carry instructions and carries are resolved once per
+// column (the role of the final carry pass of Algorithm 1).
+//
+// R = 2^(28 n) with n = ceil((bits + 2) / 28), so R >= 4N and results stay
+// in [0, 2N) without a final subtraction (Section 4, Algorithms 3 and 5).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace mx {
+
+constexpr int kLimbBits = 28;
+constexpr uint32_t kLimbMask = (1u << kLimbBits) - 1u;
+
+// Limb count of a size class: smallest n with 28 n >= bits + 2 (R >= 4N).
+constexpr int limbs_for(int bits) { return (bits + 2 + kLimbBits - 1) / kLimbBits; }
+// 64-bit words holding a value of `bits` bits.
+constexpr int words_for(int bits) { return (bits + 63) / 64; }
+
+// ---- compile-time loops ---------------------------------------------------
+template <int B, typename F, int... I>
+__device__ __forceinline__ void sfor_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, B + I>{}), ...);
+}
+// Calls f(integral_constant<int, i>) for i = B .. E-1 (nothing when E <= B).
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (E > B) sfor_impl<B>(f, std::make_integer_sequence<int, E - B>{});
+}
+
+__device__ __forceinline__ uint64_t mac(uint64_t acc, uint32_t a, uint32_t b) {
+  return acc + (uint64_t)a * (uint64_t)b;  // v_mad_u64_u32
+}
+
+// sum_{i=LO..HI} a[i] * b[K-i], two interleaved chains for issue overlap.
+template <int K, int LO, int HI, int NA, int NB>
+__device__ __forceinline__ uint64_t colsum(const uint32_t (&a)[NA], const uint32_t (&b)[NB]) {
+  uint64_t s0 = 0, s1 = 0;
+  sfor<LO, HI + 1>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    static_assert(i >= 0 && i < NA && K - i >= 0 && K - i < NB, "column index");
+    if constexpr (((i - LO) & 1) == 0)
+      s0 = mac(s0, a[i], b[K - i]);
+    else
+      s1 = mac(s1, a[i], b[K - i]);
+  });
+  return s0 + s1;
+}
+
+// ---- products (Section 2 / Algorithms 1 and 2) ----------------------------
+
+// t = a * b, 2N normalised limbs.
+template <int N>
+__device__ __forceinline__ void mul_sb(const uint32_t (&a)[N], const uint32_t (&b)[N], uint32_t (&t)[2 * N]) {
+  uint64_t carry = 0;
+  sfor<0, 2 * N - 1>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int lo = k > N - 1 ? k - (N - 1) : 0;
+    constexpr int hi = k < N - 1 ? k : N - 1;
+    uint64_t acc = colsum<k, lo, hi>(a, b) + carry;
+    t[k] = (uint32_t)acc & kLimbMask;
+    carry = acc >> kLimbBits;
+  });
+  t[2 * N - 1] = (uint32_t)carry;
+}
+
+// t = a^2: off-diagonal products once, doubled, plus the diagonal (Algorithm 2).
+template <int N>
+__device__ __forceinline__ void sqr_sb(const uint32_t (&a)[N], uint32_t (&t)[2 * N]) {
+  uint64_t carry = 0;
+  sfor<0, 2 * N - 1>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int lo = k > N - 1 ? k - (N - 1) : 0;
+    constexpr int hi = (k + 1) / 2 - 1;  // i < k - i
+    uint64_t acc = (colsum<k, lo, hi>(a, a) << 1) + carry;
+    if constexpr ((k & 1) == 0) acc = mac(acc, a[k / 2], a[k / 2]);
+    t[k] = (uint32_t)acc & kLimbMask;
+    carry = acc >> kLimbBits;
+  });
+  t[2 * N - 1] = (uint32_t)carry;
+}
+
+// ---- Montgomery reduction (Section 5) --------------------------------------
+//
+// q = (T mod R) * N' mod R                         (Algorithm 6, step 1)
+// TRUNC: only the partial products q_i N_j with i + j >= n - 2 are formed
+//   (Theorem 2).  With P_w = sum_{i+j=w} q_i N_j:
+//     a2 = T[n-2] + P_{n-2},  a1 = T[n-1] + P_{n-1} + (a2 >> 28)
+//     k  = (a1 >> 28) + [(a1 | a2) mod 2^28 != 0]
+//   k is the exact carry into limb n: the skipped columns only add a carry
+//   smaller than 2^56 below column n-2, and limbs 0..n-1 of T + qN vanish
+//   (Theorem 1, equation (3)), so k = ceil((a1 2^28 + a2 mod 2^28) / 2^56).
+//   The indicator is the analogue of c_add (equation (1)).
+// PLAIN: the whole product T + q N is formed (Algorithm 3, B_fma) and the
+//   carry out of the low n limbs is propagated.
+// C = floor(T / R) + sum_{w >= n} P_w 2^{28 (w - n)} + k   (Algorithm 6, step 4)
+//
+// `mod` and `np` are read from memory limb by limb (column-major per lane).
+template <int N, bool TRUNC, typename LoadM, typename LoadNP>
+__device__ __forceinline__ void redc(const uint32_t (&t)[2 * N], LoadM&& ldm, LoadNP&& ldnp, uint32_t (&c)[N]) {
+  static_assert(N >= 3, "size class too small");
+  uint32_t q[N];
+  {
+    uint32_t np[N];
+    sfor<0, N>([&](auto I) { np[decltype(I)::value] = ldnp(decltype(I)::value); });
+    uint64_t carry = 0;
+    sfor<0, N>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      uint64_t acc = colsum<k, 0, k>(t, np) + carry;
+      q[k] = (uint32_t)acc & kLimbMask;
+      carry = acc >> kLimbBits;
+    });
+  }
+  uint32_t m[N];
+  sfor<0, N>([&](auto I) { m[decltype(I)::value] = ldm(decltype(I)::value); });
+  uint64_t carry;
+  if constexpr (TRUNC) {
+    const uint64_t a2 = colsum<N - 2, 0, N - 2>(q, m) + t[N - 2];
+    const uint64_t a1 = colsum<N - 1, 0, N - 1>(q, m) + t[N - 1] + (a2 >> kLimbBits);
+    carry = (a1 >> kLimbBits) + ((((uint32_t)a1 | (uint32_t)a2) & kLimbMask) != 0u ? 1u : 0u);
+  } else {
+    carry = 0;
+    sfor<0, N>([&](auto W) {
+      constexpr int w = decltype(W)::value;
+      uint64_t acc = colsum<w, 0, w>(q, m) + t[w] + carry;
+      carry = acc >> kLimbBits;  // low 28 bits are zero: T + qN = 0 mod R
+    });
+  }
+  sfor<N, 2 * N - 1>([&](auto W) {
+    constexpr int w = decltype(W)::value;
+    uint64_t acc = colsum<w, w - (N - 1), N - 1>(q, m) + t[w] + carry;
+    c[w - N] = (uint32_t)acc & kLimbMask;
+    carry = acc >> kLimbBits;
+  });
+  c[N - 1] = (uint32_t)(carry + t[2 * N - 1]);
+}
+
+// ---- layout: 64-bit words <-> 28-bit limbs (expand / contract, Section 6) -
+
+// x = the low 28 N bits of the W-word little-endian value at src.
+template <int N, int W>
+__device__ __forceinline__ void expand(const uint64_t* __restrict__ src, uint32_t (&x)[N]) {
+  uint64_t w[W];
+  sfor<0, W>([&](auto J) { w[decltype(J)::value] = src[decltype(J)::value]; });
+  sfor<0, N>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int bit = kLimbBits * i, wd = bit / 64, off = bit % 64;
+    uint64_t v = 0;
+    if constexpr (wd < W) v = w[wd] >> off;
+    if constexpr (off > 64 - kLimbBits && wd + 1 < W) v |= w[wd + 1] << (64 - off);
+    x[i] = (uint32_t)v & kLimbMask;
+  });
+}
+
+// dst = the W-word value of the limbs x (bits beyond 64 W are dropped).
+template <int N, int W>
+__device__ __forceinline__ void contract(const uint32_t (&x)[N], uint64_t* __restrict__ dst) {
+  sfor<0, W>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    uint64_t v = 0;
+    sfor<0, N>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int lo = kLimbBits * i - 64 * j;  // bit position of limb i inside word j
+      if constexpr (lo > -kLimbBits && lo < 64) {
+        if constexpr (lo >= 0)
+          v |= (uint64_t)x[i] << lo;
+        else
+          v |= (uint64_t)x[i] >> (-lo);
+      }
+    });
+    dst[j] = v;
+  });
+}
+
+// c = x - m if x >= m else x (constant time; x <= m on entry gives [0, m)).
+template <int N>
+__device__ __forceinline__ void canon(uint32_t (&x)[N], const uint32_t (&m)[N]) {
+  uint32_t d[N];
+  int64_t br = 0;
+  sfor<0, N>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    int64_t v = (int64_t)x[i] - (int64_t)m[i] + br;
+    d[i] = (uint32_t)v & kLimbMask;
+    br = v >> kLimbBits;  // 0 or -1
+  });
+  const uint32_t keep = (uint32_t)(br != 0 ? 0xFFFFFFFFu : 0u);  // borrow => x < m => keep x
+  sfor<0, N>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    x[i] = (x[i] & keep) | (d[i] & ~keep);
+  });
+}
+
+}  // namespace mx

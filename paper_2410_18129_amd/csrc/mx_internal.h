@@ -1,0 +1,51 @@
+// Internal interface between the C ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mx {
+
+// Device context arrays, limb-major: limb i of context c at arr[i * stride + c].
+struct CtxDev {
+  uint32_t* n;   // modulus N
+  uint32_t* np;  // N' = -N^{-1} mod R
+  uint32_t* r2;  // R^2 mod N
+  uint32_t* r1;  // R mod N (Montgomery form of 1)
+  uint32_t count;
+  uint32_t stride;
+};
+
+// Launchers of one size class (one instantiation of the kernel templates).
+struct ClassOps {
+  int bits;
+  int limbs;
+  hipError_t (*ctx_init)(const uint64_t* mods, const CtxDev& ctx, hipStream_t st);
+  hipError_t (*mont)(bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
+                     const uint64_t* b, uint64_t* out, uint32_t count, hipStream_t st);
+  hipError_t (*modexp)(bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
+                       const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out,
+                       uint32_t count, uint32_t* table, uint32_t tstride, hipStream_t st);
+};
+
+// Size classes built into the library.
+#define MX_FOR_EACH_CLASS(X) X(64) X(128) X(256) X(512) X(1024) X(2048)
+
+#define MX_DECL_CLASS(B) const ClassOps* class_ops_##B();
+MX_FOR_EACH_CLASS(MX_DECL_CLASS)
+#undef MX_DECL_CLASS
+
+// nullptr for an unsupported class
+inline const ClassOps* class_ops(uint32_t bits) {
+  switch (bits) {
+#define MX_CASE(B) \
+  case B:          \
+    return class_ops_##B();
+    MX_FOR_EACH_CLASS(MX_CASE)
+#undef MX_CASE
+    default:
+      return nullptr;
+  }
+}
+
+}  // namespace mx

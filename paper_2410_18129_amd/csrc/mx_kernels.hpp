@@ -1,0 +1,232 @@
+#pragma once
+// Batched Montgomery kernels (templates; instantiated per size class in mx_class.hip) for gfx950: context set-up, modmul / modsqr and
+// constant-time fixed-window modular exponentiation (Algorithm 7).
+// One instance per lane; see mx_core.hpp for the arithmetic.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mx_core.hpp"
+#include "mx_internal.h"
+
+namespace mx {
+
+// ---- context: N, N' = -N^{-1} mod R, R mod N, R^2 mod N (Section 4) -------
+//
+// N' by Newton lifting y <- y (2 - N y) mod R from y = N (N^2 = 1 mod 8),
+// tripling... doubling the number of correct low bits per step; R mod N and
+// R^2 mod N by 28n + 28n constant-time doublings with a conditional subtract.
+template <int N, int W>
+__global__ void __launch_bounds__(64) k_ctx_init(const uint64_t* __restrict__ mods, CtxDev ctx) {
+  const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
+  if (gid >= ctx.count) return;
+  uint32_t m[N];
+  expand<N, W>(mods + (size_t)gid * W, m);
+
+  uint32_t y[N];
+  sfor<0, N>([&](auto I) { y[decltype(I)::value] = m[decltype(I)::value]; });
+  // correct bits: 3 * 2^it >= 28 N  <=>  it >= log2(28 N / 3); 12 covers N <= 438
+#pragma nounroll
+  for (int it = 0; it < 12; ++it) {
+    uint32_t t[2 * N];
+    mul_sb<N>(m, y, t);  // low N limbs: N y mod R
+    uint32_t u[N];
+    uint32_t cy = 3;  // (R - 1 - x) + 3 = 2 - x mod R
+    sfor<0, N>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      uint32_t v = (~t[i] & kLimbMask) + cy;
+      u[i] = v & kLimbMask;
+      cy = v >> kLimbBits;
+    });
+    mul_sb<N>(y, u, t);
+    sfor<0, N>([&](auto I) { y[decltype(I)::value] = t[decltype(I)::value]; });
+  }
+  uint32_t np[N];
+  {
+    uint32_t cy = 1;  // -y mod R = (R - 1 - y) + 1
+    sfor<0, N>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      uint32_t v = (~y[i] & kLimbMask) + cy;
+      np[i] = v & kLimbMask;
+      cy = v >> kLimbBits;
+    });
+  }
+
+  uint32_t r[N];
+  sfor<0, N>([&](auto I) { r[decltype(I)::value] = 0; });
+  r[0] = 1;
+  uint32_t r1[N];
+#pragma nounroll
+  for (int s = 0; s < 2 * kLimbBits * N; ++s) {
+    // r = 2 r (r < N <= R/4 so no limb overflows), then subtract N if r >= N
+    uint32_t top = 0;
+    sfor<0, N>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      uint32_t v = (r[i] << 1) | top;
+      top = r[i] >> (kLimbBits - 1);
+      r[i] = v & kLimbMask;
+    });
+    canon<N>(r, m);
+    if (s == kLimbBits * N - 1) {
+      sfor<0, N>([&](auto I) { r1[decltype(I)::value] = r[decltype(I)::value]; });
+    }
+  }
+  sfor<0, N>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const size_t o = (size_t)i * ctx.stride + gid;
+    ctx.n[o] = m[i];
+    ctx.np[o] = np[i];
+    ctx.r1[o] = r1[i];
+    ctx.r2[o] = r[i];
+  });
+}
+
+// ---- batched modmul / modsqr ---------------------------------------------
+// out = REDC(a * b) (or REDC(a^2)) for each instance, values of RW words.
+template <int N, int RW, bool TRUNC, bool SQR>
+__global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restrict__ cidx,
+                                             const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                                             uint64_t* __restrict__ out, uint32_t count) {
+  const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
+  const bool live = gid < count;
+  const uint32_t inst = live ? gid : count - 1;
+  uint32_t c = cidx ? cidx[inst] : inst;
+  c = c < ctx.count ? c : 0u;
+  const uint32_t* cn = ctx.n + c;
+  const uint32_t* cnp = ctx.np + c;
+  const size_t cs = ctx.stride;
+
+  uint32_t x[N];
+  expand<N, RW>(a + (size_t)inst * RW, x);
+  uint32_t t[2 * N];
+  if constexpr (SQR) {
+    sqr_sb<N>(x, t);
+  } else {
+    uint32_t y[N];
+    expand<N, RW>(b + (size_t)inst * RW, y);
+    mul_sb<N>(x, y, t);
+  }
+  uint32_t r[N];
+  redc<N, TRUNC>(t, [&](int i) { return cn[i * cs]; }, [&](int i) { return cnp[i * cs]; }, r);
+  if (live) contract<N, RW>(r, out + (size_t)inst * RW);
+}
+
+// ---- constant-time fixed-window exponentiation (Algorithm 7) --------------
+//
+// Per lane: A~ = REDC(base * R^2); table G[0] = R mod N, G[1] = A~,
+// G[i] = REDC(G[i-1] A~); Y = G[top window]; for each further window:
+// w squarings, a full masked scan of the table, one multiplication;
+// finally REDC(Y) and one conditional subtraction.  Every branch depends
+// only on public values (step counter, window size, exponent length); the
+// table addresses depend only on the entry counter.
+//
+// The whole schedule runs through one loop so that the squaring code, the
+// multiplication code and the reduction each exist once in the binary.
+enum StepKind : int { kSqr = 0, kMulR2 = 1, kMulG1 = 2, kMulSel = 3, kMulOne = 4, kLoadSel = 5 };
+
+template <int N, int BW, bool TRUNC>
+__global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __restrict__ cidx,
+                                               const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
+                                               uint32_t ebits, uint32_t ewords, uint32_t w,
+                                               uint64_t* __restrict__ out, uint32_t count,
+                                               uint32_t* __restrict__ table, uint32_t tstride) {
+  const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
+  const bool live = gid < count;
+  const uint32_t inst = live ? gid : count - 1;
+  uint32_t c = cidx ? cidx[inst] : inst;
+  c = c < ctx.count ? c : 0u;
+  const uint32_t* cn = ctx.n + c;
+  const uint32_t* cnp = ctx.np + c;
+  const size_t cs = ctx.stride;
+  uint32_t* tab = table + gid;  // entry e, limb i at tab[(e * N + i) * tstride]
+  const size_t ts = tstride;
+  const uint64_t* e64 = ex + (size_t)inst * ewords;
+
+  const uint32_t nent = 1u << w;
+  const uint32_t nwin = ebits ? (ebits + w - 1) / w : 1u;
+
+  // G[0] = R mod N
+  for (int i = 0; i < N; ++i) tab[(size_t)i * ts] = ctx.r1[(size_t)i * cs + c];
+
+  uint32_t y[N];
+  expand<N, BW>(base + (size_t)inst * BW, y);
+
+  const uint32_t n_tab = nent - 1;              // REDC(base R^2), then nent - 2 table products
+  const uint32_t n_main = (nwin - 1) * (w + 1);  // per window: w squarings + 1 product
+  const uint32_t total = n_tab + 1 + n_main + 1;
+
+#pragma nounroll
+  for (uint32_t s = 0; s < total; ++s) {
+    int kind;
+    int store_e = -1;
+    uint32_t win = 0;
+    if (s < n_tab) {
+      kind = s == 0 ? kMulR2 : kMulG1;
+      store_e = (int)s + 1;
+    } else if (s == n_tab) {
+      kind = kLoadSel;
+      win = nwin - 1;
+    } else if (s < n_tab + 1 + n_main) {
+      const uint32_t r = s - n_tab - 1;
+      win = nwin - 2 - r / (w + 1);
+      kind = (r % (w + 1)) < w ? kSqr : kMulSel;
+    } else {
+      kind = kMulOne;
+    }
+
+    uint32_t bsrc[N];
+    if (kind == kMulSel || kind == kLoadSel) {
+      // window bits [win w, win w + w) of the exponent, clipped to ebits
+      const uint32_t p = win * w;
+      const uint32_t width = ebits > p ? (ebits - p < w ? ebits - p : w) : 0u;
+      const uint32_t lo = p >> 6, sh = p & 63;
+      uint64_t v = (width > 0 && lo < ewords) ? e64[lo] >> sh : 0ull;
+      if (width > 0 && sh + width > 64 && lo + 1 < ewords) v |= e64[lo + 1] << (64 - sh);
+      const uint32_t bits = (uint32_t)v & ((1u << width) - 1u);
+      // full masked scan: every entry is read, the selected one survives
+      sfor<0, N>([&](auto I) { bsrc[decltype(I)::value] = 0; });
+#pragma nounroll
+      for (uint32_t e = 0; e < nent; ++e) {
+        const uint32_t mask = e == bits ? 0xFFFFFFFFu : 0u;
+        const uint32_t* g = tab + (size_t)e * N * ts;
+        sfor<0, N>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          bsrc[i] |= g[(size_t)i * ts] & mask;
+        });
+      }
+      if (kind == kLoadSel) {
+        sfor<0, N>([&](auto I) { y[decltype(I)::value] = bsrc[decltype(I)::value]; });
+        continue;
+      }
+    } else if (kind == kMulR2 || kind == kMulG1) {
+      const uint32_t* src = kind == kMulR2 ? ctx.r2 + c : tab + (size_t)N * ts;
+      const size_t st = kind == kMulR2 ? cs : ts;
+      sfor<0, N>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        bsrc[i] = src[(size_t)i * st];
+      });
+    } else if (kind == kMulOne) {
+      sfor<0, N>([&](auto I) { bsrc[decltype(I)::value] = decltype(I)::value == 0 ? 1u : 0u; });
+    }
+
+    uint32_t t[2 * N];
+    if (kind == kSqr)
+      sqr_sb<N>(y, t);
+    else
+      mul_sb<N>(y, bsrc, t);
+    redc<N, TRUNC>(t, [&](int i) { return cn[(size_t)i * cs]; }, [&](int i) { return cnp[(size_t)i * cs]; }, y);
+    if (store_e >= 0) {
+      uint32_t* g = tab + (size_t)store_e * N * ts;
+      sfor<0, N>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        g[(size_t)i * ts] = y[i];
+      });
+    }
+  }
+  uint32_t m[N];
+  sfor<0, N>([&](auto I) { m[decltype(I)::value] = cn[(size_t)decltype(I)::value * cs]; });
+  canon<N>(y, m);
+  if (live) contract<N, BW>(y, out + (size_t)inst * BW);
+}
+
+
+}  // namespace mx

@@ -1,0 +1,220 @@
+"""ctypes binding of libmontexp.so (C ABI in include/montexp.h).
+
+Argument marshalling only: every arithmetic step runs in the library's HIP
+kernels.  Device buffers are torch tensors (int64 words holding the raw
+64-bit limbs of each value, one row per instance) and streams are torch
+streams; torch is used for device memory and streams, nothing else.  If the
+library is missing this module raises -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmontexp.so")
+
+MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EUNSUPPORTED = 0, 1, 2, 3, 4
+MX_REDC_TRUNC, MX_REDC_PLAIN = 0, 1
+SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048)
+LIMB_BITS = 28
+
+# exported symbols and their ctypes signatures (mirrors include/montexp.h)
+_P = ctypes.c_void_p
+_U32 = ctypes.c_uint32
+_SIGS = {
+    "mont_ctx_init": (ctypes.c_int, [ctypes.POINTER(_P), _P, _U32, _U32, _P]),
+    "mont_ctx_query": (ctypes.c_int, [_P, ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.POINTER(_U32),
+                                      ctypes.POINTER(_U32), ctypes.POINTER(ctypes.c_size_t)]),
+    "mont_ctx_export": (ctypes.c_int, [_P, _U32, _P, _P, _P]),
+    "mont_ctx_destroy": (None, [_P]),
+    "mont_mul_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _U32, _U32, _P]),
+    "mont_sqr_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P]),
+    "modexp_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P]),
+    "mont_last_error": (ctypes.c_char_p, []),
+}
+EXPORTS = tuple(_SIGS)
+
+_lib = None
+
+
+class MontError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (status %d)" % (msg, status))
+        self.status = status
+
+
+def lib():
+    """Loads libmontexp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmontexp.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2410_18129_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != MX_OK:
+        msg = lib().mont_last_error().decode(errors="replace")
+        raise MontError(st, msg)
+
+
+def words_for(bits):
+    return (bits + 63) // 64
+
+
+def limbs_for(bits):
+    return (bits + 2 + LIMB_BITS - 1) // LIMB_BITS
+
+
+def r_bits_for(bits):
+    return LIMB_BITS * limbs_for(bits)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_words(x, words, device):
+    """numpy uint64 [n, words] / torch tensor -> contiguous int64 device tensor."""
+    import torch
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.uint64).view(np.int64))
+    if x.dtype != torch.int64 or x.dim() != 2 or x.shape[1] != words:
+        raise ValueError("expected an int64 tensor of shape [n, %d]" % words)
+    return x.to(device).contiguous()
+
+
+class Context:
+    """Device-resident Montgomery contexts for a batch of moduli of one size class."""
+
+    def __init__(self, moduli_words, bits, stream=None):
+        moduli_words = np.ascontiguousarray(moduli_words, dtype=np.uint64)
+        if moduli_words.ndim != 2 or moduli_words.shape[1] != words_for(bits):
+            raise ValueError("moduli must be uint64 [count, ceil(bits/64)]")
+        self._h = ctypes.c_void_p()
+        L = lib()
+        _check(L.mont_ctx_init(ctypes.byref(self._h), moduli_words.ctypes.data_as(_P), bits,
+                               moduli_words.shape[0], _stream_ptr(stream)))
+        b, rb, lb, cnt = _U32(), _U32(), _U32(), _U32()
+        nb = ctypes.c_size_t()
+        _check(L.mont_ctx_query(self._h, ctypes.byref(b), ctypes.byref(rb), ctypes.byref(lb), ctypes.byref(cnt),
+                                ctypes.byref(nb)))
+        self.bits, self.r_bits, self.limb_bits, self.count = b.value, rb.value, lb.value, cnt.value
+        self.words = words_for(self.bits)
+        self.mont_words = words_for(self.r_bits)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("context destroyed")
+        return self._h
+
+    def device_bytes(self):
+        nb = ctypes.c_size_t()
+        _check(lib().mont_ctx_query(self.handle, None, None, None, None, ctypes.byref(nb)))
+        return nb.value
+
+    def export(self, idx):
+        """(N' mod R, R^2 mod N, R mod N) of context idx as Python ints."""
+        arrs = [np.zeros(self.mont_words, dtype=np.uint64) for _ in range(3)]
+        _check(lib().mont_ctx_export(self.handle, idx, *[a.ctypes.data_as(_P) for a in arrs]))
+        return tuple(int.from_bytes(a.tobytes(), "little") for a in arrs)
+
+    def close(self):
+        if self._h:
+            lib().mont_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_rows(name, t, n, words):
+    """Shape/dtype/device checks that keep every kernel access inside the buffers."""
+    import torch
+    if t.dtype != torch.int64 or t.dim() != 2 or t.shape[0] != n or t.shape[1] != words:
+        raise ValueError("%s: expected int64 [%d, %d], got %s %s" % (name, n, words, t.dtype, tuple(t.shape)))
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s: expected a contiguous device tensor" % name)
+
+
+def _check_idx(ctx_idx, n, ctx):
+    import torch
+    if ctx_idx is None:
+        if n > ctx.count:
+            raise ValueError("n=%d exceeds the context count %d (pass ctx_idx)" % (n, ctx.count))
+        return
+    if ctx_idx.dtype != torch.int32 or ctx_idx.dim() != 1 or ctx_idx.shape[0] != n or not ctx_idx.is_cuda:
+        raise ValueError("ctx_idx: expected int32 device tensor [%d]" % n)
+
+
+def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None):
+    """REDC(a*b) per instance; a, b: int64 device tensors [n, mont_words]."""
+    n = a.shape[0]
+    if out is None:
+        import torch
+        out = torch.empty_like(a)
+    for nm, t in (("a", a), ("b", b), ("out", out)):
+        _check_rows(nm, t, n, ctx.mont_words)
+    _check_idx(ctx_idx, n, ctx)
+    _check(lib().mont_mul_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(b), _ptr(out), n,
+                                MX_REDC_PLAIN if plain else MX_REDC_TRUNC, _stream_ptr(stream)))
+    return out
+
+
+def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None):
+    """REDC(a^2) per instance; a: int64 device tensor [n, mont_words]."""
+    n = a.shape[0]
+    if out is None:
+        import torch
+        out = torch.empty_like(a)
+    for nm, t in (("a", a), ("out", out)):
+        _check_rows(nm, t, n, ctx.mont_words)
+    _check_idx(ctx_idx, n, ctx)
+    _check(lib().mont_sqr_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(out), n,
+                                MX_REDC_PLAIN if plain else MX_REDC_TRUNC, _stream_ptr(stream)))
+    return out
+
+
+def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None):
+    """base^exp mod N per instance; base: int64 [n, words], exp: int64 [n, ceil(exp_bits/64)]."""
+    n = base.shape[0]
+    if out is None:
+        import torch
+        out = torch.empty_like(base)
+    for nm, t in (("base", base), ("out", out)):
+        _check_rows(nm, t, n, ctx.words)
+    if exp_bits:
+        _check_rows("exp", exp, n, words_for(exp_bits))
+    _check_idx(ctx_idx, n, ctx)
+    _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,
+                              window, _ptr(out), n, MX_REDC_PLAIN if plain else MX_REDC_TRUNC,
+                              _stream_ptr(stream)))
+    return out
+
+
+def to_device(words_u64, device="cuda"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(words_u64, dtype=np.uint64).view(np.int64)).to(device)
+
+
+def to_host(t):
+    return t.cpu().numpy().view(np.uint64)

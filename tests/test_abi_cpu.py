@@ -1,0 +1,52 @@
+"""Host-side checks that need no GPU: the library loads and exports the header's symbols."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "montexp.h")
+LIB = os.path.join(ROOT, "paper_2410_18129_amd", "libmontexp.so")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", src)) - {"if", "sizeof"})
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for f in ("mont_ctx_init", "mont_ctx_query", "mont_ctx_export", "mont_ctx_destroy", "mont_mul_batch",
+              "mont_sqr_batch", "modexp_batch", "mont_last_error"):
+        assert f in fns
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmontexp.so not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    for f in header_functions():
+        assert hasattr(L, f), f
+    from paper_2410_18129_amd import montexp
+    assert set(montexp.EXPORTS) == set(header_functions())
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmontexp.so not built")
+def test_host_side_argument_errors_without_gpu():
+    """Argument checks return MX_EINVAL before touching a device."""
+    from paper_2410_18129_amd import montexp as mx
+    L = mx.lib()
+    h = ctypes.c_void_p()
+    import numpy as np
+    even = np.array([[4]], dtype=np.uint64)
+    assert L.mont_ctx_init(ctypes.byref(h), even.ctypes.data_as(ctypes.c_void_p), 64, 1, None) == mx.MX_EINVAL
+    assert b"even" in L.mont_last_error()
+    one = np.array([[1]], dtype=np.uint64)
+    assert L.mont_ctx_init(ctypes.byref(h), one.ctypes.data_as(ctypes.c_void_p), 64, 1, None) == mx.MX_EINVAL
+    odd = np.array([[7]], dtype=np.uint64)
+    assert L.mont_ctx_init(ctypes.byref(h), odd.ctypes.data_as(ctypes.c_void_p), 96, 1, None) == mx.MX_EINVAL
+    assert b"size class" in L.mont_last_error()
+    assert L.mont_ctx_init(ctypes.byref(h), odd.ctypes.data_as(ctypes.c_void_p), 64, 0, None) == mx.MX_EINVAL
+    assert L.mont_mul_batch(None, None, None, None, None, 1, 0, None) == mx.MX_EINVAL
+    assert L.modexp_batch(None, None, None, None, 8, 5, None, 1, 0, None) == mx.MX_EINVAL
