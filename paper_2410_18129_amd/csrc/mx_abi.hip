@@ -33,6 +33,7 @@ uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 uint32_t default_window(uint32_t bits) {
   if (bits <= 128) return 3;
   if (bits <= 512) return 4;
+  if (bits <= 2048) return 3;  // measured best at 2048 bits: the table stays in the last-level cache
   if (bits <= 3072) return 5;
   return 6;
 }
@@ -219,8 +220,14 @@ mx_status modexp_batch(const mont_ctx* cctx, const uint32_t* ctx_idx, const uint
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   const uint32_t w = window ? window : default_window(ctx->bits);
   const uint32_t ewords = (exp_bits + 63) / 64;
-  const uint32_t tstride = round_up(n, 64);
-  const size_t need = ((size_t)1 << w) * ctx->limbs * tstride * sizeof(uint32_t);
+  const uint32_t W = words_for(ctx->bits);
+  // instances per launch: the launch's table (2^w entries x limbs x padded count) must fit one descriptor
+  const size_t per_inst = ((size_t)1 << w) * ctx->limbs * sizeof(uint32_t);
+  uint32_t chunk = (uint32_t)((mx::kMaxTableBytes / per_inst) / 64 * 64);
+  if (chunk == 0) return fail(MX_EUNSUPPORTED, "%s: window %u too large for this size class", name, w);
+  if (chunk > n) chunk = n;
+  const uint32_t tstride = round_up(chunk, 64);
+  const size_t need = per_inst * tstride;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
   std::lock_guard<std::mutex> lk(ctx->ws_mu);
@@ -235,9 +242,15 @@ mx_status modexp_batch(const mont_ctx* cctx, const uint32_t* ctx_idx, const uint
     if (e != hipSuccess) return dev_fail(e, "modexp_batch: workspace allocation");
     ctx->ws_bytes = need;
   }
-  hipError_t e = ctx->ops->modexp(!(flags & MX_REDC_PLAIN), ctx->dev, ctx_idx, base, exp, exp_bits,
-                                   ewords, w, out, n, (uint32_t*)ctx->ws, tstride, (hipStream_t)stream);
-  if (e != hipSuccess) return dev_fail(e, name);
+  const bool trunc = !(flags & MX_REDC_PLAIN);
+  for (uint32_t off = 0; off < n; off += chunk) {
+    const uint32_t cnt = n - off < chunk ? n - off : chunk;
+    hipError_t e = ctx->ops->modexp(trunc, ctx->dev, ctx_idx ? ctx_idx + off : nullptr, base + (size_t)off * W,
+                                    exp_bits ? exp + (size_t)off * ewords : exp, exp_bits, ewords, w,
+                                    out + (size_t)off * W, cnt, (uint32_t*)ctx->ws, tstride, ctx_idx ? 0u : off,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, name);
+  }
   return MX_OK;
 }
 

@@ -39,14 +39,16 @@ hipError_t mont_fn(bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx
 
 hipError_t modexp_fn(bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base, const uint64_t* ex,
                      uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out, uint32_t count, uint32_t* table,
-                     uint32_t tstride, hipStream_t st) {
+                     uint32_t tstride, uint32_t coff, hipStream_t st) {
   const uint32_t blocks = (count + 63) / 64;
+  const size_t tbytes = ((size_t)1 << w) * kN * tstride * sizeof(uint32_t);
+  if (tbytes > 0x7FFFFFFFull) return hipErrorInvalidValue;  // one buffer descriptor spans < 2 GiB
   if (trunc)
     hipLaunchKernelGGL((k_modexp<kN, kW, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits, ewords, w,
-                       out, count, table, tstride);
+                       out, count, table, tstride, (uint32_t)tbytes, coff);
   else
     hipLaunchKernelGGL((k_modexp<kN, kW, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits, ewords,
-                       w, out, count, table, tstride);
+                       w, out, count, table, tstride, (uint32_t)tbytes, coff);
   return hipGetLastError();
 }
 

@@ -145,6 +145,87 @@ __device__ __forceinline__ void redc(const uint32_t (&t)[2 * N], LoadM&& ldm, Lo
   c[N - 1] = (uint32_t)(carry + t[2 * N - 1]);
 }
 
+// ---- reduction with N and N' staged in LDS --------------------------------
+//
+// Same arithmetic as redc() above; the modulus limbs m[j] and N' limbs np[j]
+// come from LDS (lane-private columns, [limb][lane]: consecutive lanes hit
+// consecutive banks).  Columns are formed BK at a time so every LDS word
+// read feeds up to BK products; a compiler barrier between blocks keeps the
+// loaded words short-lived instead of letting them pile up in registers.
+constexpr int kColBlock = 8;
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+// acc[d] += sum over i of a[i] * ld(K0 + d - i) for the columns K0 .. K0+BK-1,
+// restricted to ILO <= i <= IHI and JLO <= K0 + d - i <= JHI.
+template <int K0, int BK, int ILO, int IHI, int JLO, int JHI, int NA, typename Ld>
+__device__ __forceinline__ void colblock(const uint32_t (&a)[NA], Ld&& ld, uint64_t (&acc)[BK]) {
+  constexpr int jmin = (K0 - IHI) > JLO ? (K0 - IHI) : JLO;
+  constexpr int jmax = (K0 + BK - 1 - ILO) < JHI ? (K0 + BK - 1 - ILO) : JHI;
+  sfor<jmin, jmax + 1>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    const uint32_t v = ld(j);
+    sfor<0, BK>([&](auto D) {
+      constexpr int d = decltype(D)::value;
+      constexpr int i = K0 + d - j;
+      if constexpr (i >= ILO && i <= IHI) acc[d] = mac(acc[d], a[i], v);
+    });
+  });
+}
+
+template <int N, bool TRUNC, typename LoadM, typename LoadNP>
+__device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm, LoadNP&& ldnp, uint32_t (&c)[N]) {
+  static_assert(N >= 3, "size class too small");
+  constexpr int BK = kColBlock;
+  uint32_t q[N];
+  // q = T_lo * N' mod R: columns 0 .. N-1, column k = sum_{i<=k} t[i] np[k-i]
+  uint64_t carry = 0;
+  sfor<0, (N + BK - 1) / BK>([&](auto B) {
+    constexpr int k0 = decltype(B)::value * BK;
+    constexpr int bk = (N - k0) < BK ? (N - k0) : BK;
+    uint64_t acc[bk];
+    sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
+    colblock<k0, bk, 0, N - 1, 0, N - 1>(t, ldnp, acc);
+    sfor<0, bk>([&](auto D) {
+      constexpr int d = decltype(D)::value;
+      const uint64_t v = acc[d] + carry;
+      q[k0 + d] = (uint32_t)v & kLimbMask;
+      carry = v >> kLimbBits;
+    });
+    compiler_fence();
+  });
+  // q * N: columns from n-2 (truncated, Theorem 2) or 0 (plain) to 2n-2
+  constexpr int W0 = TRUNC ? N - 2 : 0;
+  constexpr int NCOL = 2 * N - 1 - W0;
+  carry = 0;
+  uint64_t a2 = 0;
+  sfor<0, (NCOL + BK - 1) / BK>([&](auto B) {
+    constexpr int w0 = W0 + decltype(B)::value * BK;
+    constexpr int bk = (2 * N - 1 - w0) < BK ? (2 * N - 1 - w0) : BK;
+    uint64_t acc[bk];
+    sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = t[w0 + decltype(D)::value]; });
+    colblock<w0, bk, 0, N - 1, 0, N - 1>(q, ldm, acc);
+    sfor<0, bk>([&](auto D) {
+      constexpr int d = decltype(D)::value;
+      constexpr int w = w0 + d;
+      if constexpr (TRUNC && w == N - 2) {
+        a2 = acc[d];
+      } else if constexpr (TRUNC && w == N - 1) {
+        const uint64_t a1 = acc[d] + (a2 >> kLimbBits);
+        carry = (a1 >> kLimbBits) + ((((uint32_t)a1 | (uint32_t)a2) & kLimbMask) != 0u ? 1u : 0u);
+      } else if constexpr (w < N) {
+        carry = (acc[d] + carry) >> kLimbBits;  // low limbs of T + qN vanish
+      } else {
+        const uint64_t v = acc[d] + carry;
+        c[w - N] = (uint32_t)v & kLimbMask;
+        carry = v >> kLimbBits;
+      }
+    });
+    compiler_fence();
+  });
+  c[N - 1] = (uint32_t)(carry + t[2 * N - 1]);
+}
+
 // ---- layout: 64-bit words <-> 28-bit limbs (expand / contract, Section 6) -
 
 // x = the low 28 N bits of the W-word little-endian value at src.

@@ -25,8 +25,11 @@ struct ClassOps {
                      const uint64_t* b, uint64_t* out, uint32_t count, hipStream_t st);
   hipError_t (*modexp)(bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
                        const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out,
-                       uint32_t count, uint32_t* table, uint32_t tstride, hipStream_t st);
+                       uint32_t count, uint32_t* table, uint32_t tstride, uint32_t coff, hipStream_t st);
 };
+
+// Largest table one launch may use: a buffer descriptor spans < 2 GiB.
+constexpr size_t kMaxTableBytes = 0x7FFFFFFFull;
 
 // Size classes built into the library.
 #define MX_FOR_EACH_CLASS(X) X(64) X(128) X(256) X(512) X(1024) X(2048)

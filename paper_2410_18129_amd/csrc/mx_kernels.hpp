@@ -10,6 +10,30 @@
 
 namespace mx {
 
+// Raw buffer descriptor over `bytes` bytes at p (gfx9 word 3: 32-bit untyped
+// dwords).  Buffer accesses take a per-lane byte offset plus a uniform scalar
+// offset (no per-load address arithmetic) and are bounds-checked by the
+// hardware: an out-of-range load returns 0, an out-of-range store is dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_buf(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ uint32_t bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
+}
+
+// Copies this lane's N and N' limbs into its LDS column ([limb][lane]).  Each
+// lane reads back only its own column, so no barrier is needed.
+template <int N>
+__device__ __forceinline__ void stage_ctx(uint32_t* s_ctx, const uint32_t* cn, const uint32_t* cnp, size_t cs) {
+  for (int i = 0; i < N; ++i) {
+    s_ctx[i * 64 + threadIdx.x] = cn[(size_t)i * cs];
+    s_ctx[(N + i) * 64 + threadIdx.x] = cnp[(size_t)i * cs];
+  }
+}
+
 // ---- context: N, N' = -N^{-1} mod R, R mod N, R^2 mod N (Section 4) -------
 //
 // N' by Newton lifting y <- y (2 - N y) mod R from y = N (N^2 = 1 mod 8),
@@ -95,6 +119,9 @@ __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restr
   const uint32_t* cnp = ctx.np + c;
   const size_t cs = ctx.stride;
 
+  __shared__ uint32_t s_ctx[2 * N * 64];
+  stage_ctx<N>(s_ctx, cn, cnp, cs);
+
   uint32_t x[N];
   expand<N, RW>(a + (size_t)inst * RW, x);
   uint32_t t[2 * N];
@@ -106,7 +133,8 @@ __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restr
     mul_sb<N>(x, y, t);
   }
   uint32_t r[N];
-  redc<N, TRUNC>(t, [&](int i) { return cn[i * cs]; }, [&](int i) { return cnp[i * cs]; }, r);
+  const uint32_t* sm = s_ctx + threadIdx.x;
+  redc_blk<N, TRUNC>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, r);
   if (live) contract<N, RW>(r, out + (size_t)inst * RW);
 }
 
@@ -128,24 +156,31 @@ __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __res
                                                const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                uint32_t ebits, uint32_t ewords, uint32_t w,
                                                uint64_t* __restrict__ out, uint32_t count,
-                                               uint32_t* __restrict__ table, uint32_t tstride) {
+                                               uint32_t* __restrict__ table, uint32_t tstride, uint32_t tbytes,
+                                               uint32_t coff) {
   const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
   const bool live = gid < count;
   const uint32_t inst = live ? gid : count - 1;
-  uint32_t c = cidx ? cidx[inst] : inst;
+  uint32_t c = cidx ? cidx[inst] : inst + coff;
   c = c < ctx.count ? c : 0u;
   const uint32_t* cn = ctx.n + c;
   const uint32_t* cnp = ctx.np + c;
   const size_t cs = ctx.stride;
-  uint32_t* tab = table + gid;  // entry e, limb i at tab[(e * N + i) * tstride]
-  const size_t ts = tstride;
+  // table: entry e, limb i of this lane at byte (e * N + i) * tstride * 4 + gid * 4
+  const __amdgpu_buffer_rsrc_t tr = make_buf(table, tbytes);
+  const uint32_t tvo = gid * 4u;
+  const uint32_t tls = tstride * 4u;  // bytes between consecutive limbs
   const uint64_t* e64 = ex + (size_t)inst * ewords;
 
   const uint32_t nent = 1u << w;
   const uint32_t nwin = ebits ? (ebits + w - 1) / w : 1u;
 
+  __shared__ uint32_t s_ctx[2 * N * 64];
+  stage_ctx<N>(s_ctx, cn, cnp, cs);
+  const uint32_t* sm = s_ctx + threadIdx.x;
+
   // G[0] = R mod N
-  for (int i = 0; i < N; ++i) tab[(size_t)i * ts] = ctx.r1[(size_t)i * cs + c];
+  for (int i = 0; i < N; ++i) bstore(tr, ctx.r1[(size_t)i * cs + c], tvo, (uint32_t)i * tls);
 
   uint32_t y[N];
   expand<N, BW>(base + (size_t)inst * BW, y);
@@ -184,13 +219,21 @@ __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __res
       const uint32_t bits = (uint32_t)v & ((1u << width) - 1u);
       // full masked scan: every entry is read, the selected one survives
       sfor<0, N>([&](auto I) { bsrc[decltype(I)::value] = 0; });
+      // two entries per iteration keep 2N loads in flight (nent >= 2)
 #pragma nounroll
-      for (uint32_t e = 0; e < nent; ++e) {
-        const uint32_t mask = e == bits ? 0xFFFFFFFFu : 0u;
-        const uint32_t* g = tab + (size_t)e * N * ts;
+      for (uint32_t e = 0; e < nent; e += 2) {
+        const uint32_t mask0 = e == bits ? 0xFFFFFFFFu : 0u;
+        const uint32_t mask1 = e + 1 == bits ? 0xFFFFFFFFu : 0u;
+        const uint32_t s0 = e * (uint32_t)N * tls;
+        uint32_t v0[N], v1[N];
         sfor<0, N>([&](auto I) {
           constexpr int i = decltype(I)::value;
-          bsrc[i] |= g[(size_t)i * ts] & mask;
+          v0[i] = bload(tr, tvo, s0 + (uint32_t)i * tls);
+          v1[i] = bload(tr, tvo, s0 + (uint32_t)(N + i) * tls);
+        });
+        sfor<0, N>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          bsrc[i] |= (v0[i] & mask0) | (v1[i] & mask1);
         });
       }
       if (kind == kLoadSel) {
@@ -198,12 +241,18 @@ __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __res
         continue;
       }
     } else if (kind == kMulR2 || kind == kMulG1) {
-      const uint32_t* src = kind == kMulR2 ? ctx.r2 + c : tab + (size_t)N * ts;
-      const size_t st = kind == kMulR2 ? cs : ts;
-      sfor<0, N>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        bsrc[i] = src[(size_t)i * st];
-      });
+      if (kind == kMulR2) {
+        const uint32_t* src = ctx.r2 + c;
+        sfor<0, N>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          bsrc[i] = src[(size_t)i * cs];
+        });
+      } else {
+        sfor<0, N>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          bsrc[i] = bload(tr, tvo, (uint32_t)(N + i) * tls);
+        });
+      }
     } else if (kind == kMulOne) {
       sfor<0, N>([&](auto I) { bsrc[decltype(I)::value] = decltype(I)::value == 0 ? 1u : 0u; });
     }
@@ -213,17 +262,17 @@ __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __res
       sqr_sb<N>(y, t);
     else
       mul_sb<N>(y, bsrc, t);
-    redc<N, TRUNC>(t, [&](int i) { return cn[(size_t)i * cs]; }, [&](int i) { return cnp[(size_t)i * cs]; }, y);
+    redc_blk<N, TRUNC>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, y);
     if (store_e >= 0) {
-      uint32_t* g = tab + (size_t)store_e * N * ts;
+      const uint32_t s0 = (uint32_t)store_e * (uint32_t)N * tls;
       sfor<0, N>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        g[(size_t)i * ts] = y[i];
+        bstore(tr, y[i], tvo, s0 + (uint32_t)i * tls);
       });
     }
   }
   uint32_t m[N];
-  sfor<0, N>([&](auto I) { m[decltype(I)::value] = cn[(size_t)decltype(I)::value * cs]; });
+  sfor<0, N>([&](auto I) { m[decltype(I)::value] = sm[decltype(I)::value * 64]; });
   canon<N>(y, m);
   if (live) contract<N, BW>(y, out + (size_t)inst * BW);
 }
