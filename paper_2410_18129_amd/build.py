@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmontexp.so")
-CLASSES = (64, 128, 256, 512, 1024, 2048)
+CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # hipcc flags: packed FP32 ops stay off (the kernels are integer-only anyway)

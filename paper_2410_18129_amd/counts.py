@@ -17,8 +17,16 @@ CLOCK_HZ = 2.4e9
 PEAK_MAD_PER_S = VALU_LANES * CLOCK_HZ  # 3.93e13 28x28->64 multiply-accumulates per second
 
 
+BLOCK_LIMBS = 37
+
+
 def limbs(bits):
-    return (bits + 2 + LIMB_BITS - 1) // LIMB_BITS
+    """Limbs of a size class: ceil((bits + 2) / 28), rounded up to whole 37-limb
+    blocks above 2048 bits (block-level schoolbook)."""
+    n = (bits + 2 + LIMB_BITS - 1) // LIMB_BITS
+    if bits > 2048:
+        n = BLOCK_LIMBS * ((n + BLOCK_LIMBS - 1) // BLOCK_LIMBS)
+    return n
 
 
 def op_products(n, trunc=True):

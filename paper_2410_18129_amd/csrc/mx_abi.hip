@@ -72,6 +72,29 @@ struct mont_ctx {
   size_t ws_bytes = 0;
 };
 
+// Grows the context's workspace to at least `need` bytes (caller holds ws_mu).
+static mx_status ensure_ws(mont_ctx* ctx, size_t need, const char* name) {
+  if (ctx->ws_bytes >= need) return MX_OK;
+  // the old buffer may still be read by queued work: drain before freeing
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return dev_fail(e, name);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  ctx->ws = nullptr;
+  ctx->ws_bytes = 0;
+  e = hipMalloc(&ctx->ws, need);
+  if (e != hipSuccess) return dev_fail(e, name);
+  ctx->ws_bytes = need;
+  return MX_OK;
+}
+
+// Instances per launch so that rows * padded count * 4 bytes fits one descriptor.
+static uint32_t chunk_for(uint32_t rows, uint32_t n) {
+  if (rows == 0) return n;
+  uint64_t c = (mx::kMaxWsBytes / ((uint64_t)rows * sizeof(uint32_t))) / 64 * 64;
+  if (c > n) c = n;
+  return (uint32_t)c;
+}
+
 extern "C" {
 
 const char* mont_last_error(void) { return g_err; }
@@ -192,9 +215,24 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
-  hipError_t e = ctx->ops->mont(!(flags & MX_REDC_PLAIN), sqr, ctx->dev, ctx_idx, a, b, out, n,
-                                 (hipStream_t)stream);
-  if (e != hipSuccess) return dev_fail(e, name);
+  mont_ctx* mctx = const_cast<mont_ctx*>(ctx);
+  const uint32_t rows = ctx->ops->ws_rows(false, 0);
+  const uint32_t chunk = chunk_for(rows, n);
+  if (chunk == 0) return fail(MX_EUNSUPPORTED, "%s: workspace row too large", name);
+  const uint32_t tstride = round_up(chunk, 64);
+  const size_t need = (size_t)rows * tstride * sizeof(uint32_t);
+  std::lock_guard<std::mutex> lk(mctx->ws_mu);
+  mx_status ms = ensure_ws(mctx, need, name);
+  if (ms != MX_OK) return ms;
+  const uint32_t mw = words_for(28 * ctx->limbs);
+  for (uint32_t off = 0; off < n; off += chunk) {
+    const uint32_t cnt = n - off < chunk ? n - off : chunk;
+    hipError_t e = ctx->ops->mont(!(flags & MX_REDC_PLAIN), sqr, ctx->dev, ctx_idx ? ctx_idx + off : nullptr,
+                                  a + (size_t)off * mw, b + (size_t)off * mw, out + (size_t)off * mw, cnt,
+                                  (uint32_t*)mctx->ws, tstride, (uint32_t)need, ctx_idx ? 0u : off,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, name);
+  }
   return MX_OK;
 }
 
@@ -221,34 +259,23 @@ mx_status modexp_batch(const mont_ctx* cctx, const uint32_t* ctx_idx, const uint
   const uint32_t w = window ? window : default_window(ctx->bits);
   const uint32_t ewords = (exp_bits + 63) / 64;
   const uint32_t W = words_for(ctx->bits);
-  // instances per launch: the launch's table (2^w entries x limbs x padded count) must fit one descriptor
-  const size_t per_inst = ((size_t)1 << w) * ctx->limbs * sizeof(uint32_t);
-  uint32_t chunk = (uint32_t)((mx::kMaxTableBytes / per_inst) / 64 * 64);
+  const uint32_t rows = ctx->ops->ws_rows(true, w);
+  const uint32_t chunk = chunk_for(rows, n);
   if (chunk == 0) return fail(MX_EUNSUPPORTED, "%s: window %u too large for this size class", name, w);
-  if (chunk > n) chunk = n;
   const uint32_t tstride = round_up(chunk, 64);
-  const size_t need = per_inst * tstride;
+  const size_t need = (size_t)rows * tstride * sizeof(uint32_t);
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
   std::lock_guard<std::mutex> lk(ctx->ws_mu);
-  if (ctx->ws_bytes < need) {
-    // the old buffer may still be read by queued work: drain before freeing
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return dev_fail(e, name);
-    if (ctx->ws) (void)hipFree(ctx->ws);
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
-    e = hipMalloc(&ctx->ws, need);
-    if (e != hipSuccess) return dev_fail(e, "modexp_batch: workspace allocation");
-    ctx->ws_bytes = need;
-  }
+  mx_status ms = ensure_ws(ctx, need, name);
+  if (ms != MX_OK) return ms;
   const bool trunc = !(flags & MX_REDC_PLAIN);
   for (uint32_t off = 0; off < n; off += chunk) {
     const uint32_t cnt = n - off < chunk ? n - off : chunk;
     hipError_t e = ctx->ops->modexp(trunc, ctx->dev, ctx_idx ? ctx_idx + off : nullptr, base + (size_t)off * W,
                                     exp_bits ? exp + (size_t)off * ewords : exp, exp_bits, ewords, w,
-                                    out + (size_t)off * W, cnt, (uint32_t*)ctx->ws, tstride, ctx_idx ? 0u : off,
-                                    (hipStream_t)stream);
+                                    out + (size_t)off * W, cnt, (uint32_t*)ctx->ws, tstride, (uint32_t)need,
+                                    ctx_idx ? 0u : off, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(e, name);
   }
   return MX_OK;

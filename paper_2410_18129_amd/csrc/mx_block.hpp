@@ -1,0 +1,358 @@
+// Block-level schoolbook for the large size classes (3072 and 4096 bits).
+//
+// A number of n = K H limbs is K blocks of H = 37 limbs.  Every phase of the
+// Montgomery product is a loop over block pairs (i, j), each pair handled by
+// one of four fully unrolled H-limb routines (full product, square, low half,
+// high part), so the code size does not grow with K.  The pair sets repeat,
+// one level up, the triangles of the paper:
+//   product   (Section 2): all pairs (squaring: i <= j, cross terms doubled)
+//   q         (Algorithm 6 step 1): pairs i + j <= K - 1, the low half only
+//             on the anti-diagonal i + j = K - 1
+//   q N       truncated (Theorem 2): pairs i + j >= K - 2 -- full products
+//             above the anti-diagonal, the columns >= H - 2 of the
+//             anti-diagonal products, and the single top partial product of
+//             the pairs i + j = K - 2 (global column n - 2); plain: all pairs.
+// Block results are added into redundant 32-bit limbs (each limb stays below
+// 2^32 for K <= 4) in a per-lane workspace and normalised once per phase.
+// The truncated result uses the same two-column ceil correction as redc():
+// with S the exact sum of the known columns n-2 .. 2n-1,
+// C = floor(S / 2^56) + [S mod 2^56 != 0].
+//
+// One lane per instance.  Every loop bound, branch and workspace address
+// depends only on public values (sizes, step counter, window size).
+#pragma once
+#include "mx_kernels.hpp"
+
+namespace mx {
+
+// Workspace word offsets (in limb rows) of one lane's arrays.
+template <int H, int K>
+struct BlkLayout {
+  static constexpr int n = H * K;
+  static constexpr uint32_t Y = 0;            // current value (n)
+  static constexpr uint32_t B = n;            // multiplier (n)
+  static constexpr uint32_t T = 2 * n;        // product T (2n + 1)
+  static constexpr uint32_t Q = 4 * n + 1;    // q (n)
+  static constexpr uint32_t S = 5 * n + 1;    // T + q N columns (2n + 1)
+  static constexpr uint32_t G = 7 * n + 2;    // window table (2^w n), modexp only
+  static constexpr uint32_t rows(uint32_t w) { return G + (w ? (1u << w) * (uint32_t)n : 0u); }
+};
+
+// This lane's view of a limb-major array: row r at byte r * ls + vo.
+struct LaneBuf {
+  __amdgpu_buffer_rsrc_t r;
+  uint32_t vo;
+  uint32_t ls;
+  __device__ __forceinline__ uint32_t ld(uint32_t row) const { return bload(r, vo, row * ls); }
+  __device__ __forceinline__ void st(uint32_t row, uint32_t v) const { bstore(r, v, vo, row * ls); }
+};
+
+template <int M>
+__device__ __forceinline__ void ld_rows(const LaneBuf& b, uint32_t row, uint32_t (&x)[M]) {
+  sfor<0, M>([&](auto I) { x[decltype(I)::value] = b.ld(row + decltype(I)::value); });
+}
+template <int M>
+__device__ __forceinline__ void st_rows(const LaneBuf& b, uint32_t row, const uint32_t (&x)[M]) {
+  sfor<0, M>([&](auto I) { b.st(row + decltype(I)::value, x[decltype(I)::value]); });
+}
+// rows[row + i] += mult * p[i] (redundant limbs, no carries)
+template <int M>
+__device__ __forceinline__ void add_rows(const LaneBuf& b, uint32_t row, const uint32_t (&p)[M], uint32_t mult) {
+  uint32_t x[M];
+  ld_rows<M>(b, row, x);
+  sfor<0, M>([&](auto I) { x[decltype(I)::value] += p[decltype(I)::value] * mult; });
+  st_rows<M>(b, row, x);
+}
+__device__ __forceinline__ void zero_rows(const LaneBuf& b, uint32_t row, uint32_t len) {
+#pragma nounroll
+  for (uint32_t i = 0; i < len; ++i) b.st(row + i, 0u);
+}
+// Normalises len redundant limbs in place (chunks of C limbs held in
+// registers) and returns the carry out of the top limb.
+template <int C>
+__device__ __forceinline__ uint64_t norm_rows(const LaneBuf& b, uint32_t row, uint32_t len, uint64_t carry = 0) {
+  uint32_t i = 0;
+#pragma nounroll
+  for (; i + C <= len; i += C) {
+    uint32_t x[C];
+    ld_rows<C>(b, row + i, x);
+    sfor<0, C>([&](auto I) {
+      constexpr int k = decltype(I)::value;
+      const uint64_t v = (uint64_t)x[k] + carry;
+      x[k] = (uint32_t)v & kLimbMask;
+      carry = v >> kLimbBits;
+    });
+    st_rows<C>(b, row + i, x);
+  }
+#pragma nounroll
+  for (; i < len; ++i) {
+    const uint64_t v = (uint64_t)b.ld(row + i) + carry;
+    b.st(row + i, (uint32_t)v & kLimbMask);
+    carry = v >> kLimbBits;
+  }
+  return carry;
+}
+
+// rows[dst + i] = rows[src + i] for i < len, C limbs per register batch.
+template <int C>
+__device__ __forceinline__ void copy_rows(const LaneBuf& d, uint32_t dst, const LaneBuf& sb, uint32_t src,
+                                          uint32_t len) {
+  uint32_t i = 0;
+#pragma nounroll
+  for (; i + C <= len; i += C) {
+    uint32_t x[C];
+    ld_rows<C>(sb, src + i, x);
+    st_rows<C>(d, dst + i, x);
+  }
+#pragma nounroll
+  for (; i < len; ++i) d.st(dst + i, sb.ld(src + i));
+}
+
+// One Montgomery product on the workspace: Y <- REDC(Y * B) or REDC(Y^2).
+// n = K H; context blocks come from the limb-major context arrays.
+template <int H, int K, bool TRUNC>
+__device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const LaneBuf& cn, const LaneBuf& cnp) {
+  using Lay = BlkLayout<H, K>;
+  constexpr uint32_t n = Lay::n;
+  // ---- product T = Y * B (or Y^2), Section 2 at block level --------------
+  zero_rows(ws, Lay::T, 2 * n + 1);
+#pragma nounroll
+  for (uint32_t i = 0; i < K; ++i) {
+    uint32_t a[H];
+    ld_rows<H>(ws, Lay::Y + i * H, a);
+#pragma nounroll
+    for (uint32_t j = sqr ? i : 0u; j < K; ++j) {
+      uint32_t t[2 * H];
+      if (sqr && j == i) {
+        sqr_sb<H>(a, t);
+        add_rows<2 * H>(ws, Lay::T + (i + j) * H, t, 1u);
+      } else {
+        uint32_t b[H];
+        ld_rows<H>(ws, (sqr ? Lay::Y : Lay::B) + j * H, b);
+        mul_sb<H>(a, b, t);
+        add_rows<2 * H>(ws, Lay::T + (i + j) * H, t, sqr ? 2u : 1u);
+      }
+    }
+  }
+  norm_rows<H>(ws, Lay::T, 2 * n + 1);
+  // ---- q = T_lo * N' mod R: pairs i + j <= K - 1 (Algorithm 6 step 1) ------
+  zero_rows(ws, Lay::Q, n);
+#pragma nounroll
+  for (uint32_t i = 0; i < K; ++i) {
+    uint32_t a[H];
+    ld_rows<H>(ws, Lay::T + i * H, a);
+#pragma nounroll
+    for (uint32_t j = 0; i + j < K; ++j) {
+      uint32_t b[H];
+      ld_rows<H>(cnp, j * H, b);
+      if (i + j + 1 < K) {
+        uint32_t t[2 * H];
+        mul_sb<H>(a, b, t);
+        add_rows<2 * H>(ws, Lay::Q + (i + j) * H, t, 1u);
+      } else {
+        uint32_t l[H];
+        lo_sb<H>(a, b, l);
+        add_rows<H>(ws, Lay::Q + (i + j) * H, l, 1u);
+      }
+    }
+  }
+  (void)norm_rows<H>(ws, Lay::Q, n);  // the carry out of limb n - 1 is dropped: mod R
+  // ---- S = T + q N over the needed columns ---------------------------------
+  // TRUNC: S holds columns n-2 .. 2n (row S + c is column n - 2 + c).
+  // PLAIN: S holds columns 0 .. 2n (row S + c is column c).
+  constexpr uint32_t c0 = TRUNC ? n - 2 : 0;
+  constexpr uint32_t slen = 2 * n + 1 - c0;
+  copy_rows<H>(ws, Lay::S, ws, Lay::T + c0, slen);
+#pragma nounroll
+  for (uint32_t i = 0; i < K; ++i) {
+    uint32_t a[H];
+    ld_rows<H>(ws, Lay::Q + i * H, a);
+#pragma nounroll
+    for (uint32_t j = (TRUNC && i + 2 < K) ? K - 2 - i : 0u; j < K; ++j) {
+      uint32_t b[H];
+      ld_rows<H>(cn, j * H, b);
+      if (!TRUNC || i + j >= K) {
+        uint32_t t[2 * H];
+        mul_sb<H>(a, b, t);
+        add_rows<2 * H>(ws, Lay::S + (i + j) * H - c0, t, 1u);
+      } else if (i + j + 1 == K) {
+        uint32_t v[H + 2];
+        hi_sb<H>(a, b, v);
+        add_rows<H + 2>(ws, Lay::S, v, 1u);
+      } else {  // i + j == K - 2: its top partial product sits at column n - 2
+        const uint64_t p = (uint64_t)a[H - 1] * b[H - 1];
+        uint32_t v[2] = {(uint32_t)p & kLimbMask, (uint32_t)(p >> kLimbBits)};
+        add_rows<2>(ws, Lay::S, v, 1u);
+      }
+    }
+  }
+  if constexpr (TRUNC) {
+    // exact value of columns >= n-2, then the ceil correction for the skipped columns
+    (void)norm_rows<H>(ws, Lay::S, slen);
+    const uint32_t lowz = (ws.ld(Lay::S) | ws.ld(Lay::S + 1)) != 0u ? 1u : 0u;
+    (void)norm_rows<H>(ws, Lay::S + 2, n, lowz);  // adds the correction, result < 2N < R
+    copy_rows<H>(ws, Lay::Y, ws, Lay::S + 2, n);
+  } else {
+    (void)norm_rows<H>(ws, Lay::S, slen);  // limbs 0 .. n-1 are zero: T + qN = 0 mod R
+    copy_rows<H>(ws, Lay::Y, ws, Lay::S + n, n);
+  }
+}
+
+// Loads the RW-word little-endian value at src into rows row .. row+n-1 (28-bit limbs).
+template <int H, int K>
+__device__ __forceinline__ void expand_rows(const LaneBuf& ws, uint32_t row, const uint64_t* __restrict__ src,
+                                            uint32_t words) {
+  constexpr uint32_t n = H * K;
+#pragma nounroll
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t bit = kLimbBits * i, wd = bit >> 6, off = bit & 63;
+    uint64_t v = wd < words ? src[wd] >> off : 0ull;
+    if (off > 64 - kLimbBits && wd + 1 < words) v |= src[wd + 1] << (64 - off);
+    ws.st(row + i, (uint32_t)v & kLimbMask);
+  }
+}
+
+template <int H, int K>
+__device__ __forceinline__ void contract_rows(const LaneBuf& ws, uint32_t row, uint64_t* __restrict__ dst,
+                                              uint32_t words) {
+  constexpr uint32_t n = H * K;
+#pragma nounroll
+  for (uint32_t j = 0; j < words; ++j) {
+    uint64_t v = 0;
+    const uint32_t i0 = (64 * j) / kLimbBits;
+#pragma nounroll
+    for (uint32_t i = i0; i < n && i <= i0 + 3; ++i) {
+      const int lo = (int)(kLimbBits * i) - (int)(64 * j);
+      const uint64_t x = ws.ld(row + i);
+      if (lo >= 0 && lo < 64) v |= x << lo;
+      if (lo < 0 && lo > -kLimbBits) v |= x >> (-lo);
+    }
+    dst[j] = v;
+  }
+}
+
+// ---- batched modmul / modsqr, block version ---------------------------------
+template <int H, int K, bool TRUNC, bool SQR>
+__global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
+                                                 const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                                                 uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
+                                                 uint32_t tstride, uint32_t ws_bytes, uint32_t coff) {
+  using Lay = BlkLayout<H, K>;
+  constexpr uint32_t n = Lay::n;
+  const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
+  const bool live = gid < count;
+  const uint32_t inst = live ? gid : count - 1;
+  uint32_t c = cidx ? cidx[inst] : inst + coff;
+  c = c < ctx.count ? c : 0u;
+  const uint32_t rw = (kLimbBits * n + 63) / 64;
+  const LaneBuf ws{make_buf(ws_base, ws_bytes), gid * 4u, tstride * 4u};
+  const uint32_t cbytes = n * ctx.stride * 4u;
+  const LaneBuf cn{make_buf(ctx.n, cbytes), c * 4u, ctx.stride * 4u};
+  const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
+  expand_rows<H, K>(ws, Lay::Y, a + (size_t)inst * rw, rw);
+  if (!SQR) expand_rows<H, K>(ws, Lay::B, b + (size_t)inst * rw, rw);
+  mont_blk<H, K, TRUNC>(SQR, ws, cn, cnp);
+  if (live) contract_rows<H, K>(ws, Lay::Y, out + (size_t)inst * rw, rw);
+}
+
+// ---- modexp, block version (same schedule as k_modexp) ----------------------
+template <int H, int K, bool TRUNC>
+__global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
+                                                   const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
+                                                   uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
+                                                   uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
+                                                   uint32_t tstride, uint32_t ws_bytes, uint32_t coff) {
+  using Lay = BlkLayout<H, K>;
+  constexpr uint32_t n = Lay::n;
+  const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
+  const bool live = gid < count;
+  const uint32_t inst = live ? gid : count - 1;
+  uint32_t c = cidx ? cidx[inst] : inst + coff;
+  c = c < ctx.count ? c : 0u;
+  const LaneBuf ws{make_buf(ws_base, ws_bytes), gid * 4u, tstride * 4u};
+  const uint32_t cbytes = n * ctx.stride * 4u;
+  const LaneBuf cn{make_buf(ctx.n, cbytes), c * 4u, ctx.stride * 4u};
+  const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
+  const LaneBuf cr1{make_buf(ctx.r1, cbytes), c * 4u, ctx.stride * 4u};
+  const LaneBuf cr2{make_buf(ctx.r2, cbytes), c * 4u, ctx.stride * 4u};
+  const uint64_t* e64 = ex + (size_t)inst * ewords;
+
+  const uint32_t nent = 1u << w;
+  const uint32_t nwin = ebits ? (ebits + w - 1) / w : 1u;
+  // G[0] = R mod N
+  copy_rows<H>(ws, Lay::G, cr1, 0, n);
+  expand_rows<H, K>(ws, Lay::Y, base + (size_t)inst * bw, bw);
+
+  const uint32_t n_tab = nent - 1;
+  const uint32_t n_main = (nwin - 1) * (w + 1);
+  const uint32_t total = n_tab + 1 + n_main + 1;
+#pragma nounroll
+  for (uint32_t s = 0; s < total; ++s) {
+    int kind;
+    int store_e = -1;
+    uint32_t win = 0;
+    if (s < n_tab) {
+      kind = s == 0 ? kMulR2 : kMulG1;
+      store_e = (int)s + 1;
+    } else if (s == n_tab) {
+      kind = kLoadSel;
+      win = nwin - 1;
+    } else if (s < n_tab + 1 + n_main) {
+      const uint32_t r = s - n_tab - 1;
+      win = nwin - 2 - r / (w + 1);
+      kind = (r % (w + 1)) < w ? kSqr : kMulSel;
+    } else {
+      kind = kMulOne;
+    }
+    if (kind == kMulSel || kind == kLoadSel) {
+      const uint32_t p = win * w;
+      const uint32_t width = ebits > p ? (ebits - p < w ? ebits - p : w) : 0u;
+      const uint32_t lo = p >> 6, sh = p & 63;
+      uint64_t v = (width > 0 && lo < ewords) ? e64[lo] >> sh : 0ull;
+      if (width > 0 && sh + width > 64 && lo + 1 < ewords) v |= e64[lo + 1] << (64 - sh);
+      const uint32_t bits = (uint32_t)v & ((1u << width) - 1u);
+      const uint32_t dst = kind == kLoadSel ? Lay::Y : Lay::B;
+      // full masked scan of the table, H limbs at a time
+#pragma nounroll
+      for (uint32_t blk = 0; blk < K; ++blk) {
+        uint32_t acc[H];
+        sfor<0, H>([&](auto I) { acc[decltype(I)::value] = 0; });
+#pragma nounroll
+        for (uint32_t e = 0; e < nent; e += 2) {
+          const uint32_t mask0 = e == bits ? 0xFFFFFFFFu : 0u;
+          const uint32_t mask1 = e + 1 == bits ? 0xFFFFFFFFu : 0u;
+          uint32_t g0[H], g1[H];
+          ld_rows<H>(ws, Lay::G + e * n + blk * H, g0);
+          ld_rows<H>(ws, Lay::G + (e + 1) * n + blk * H, g1);
+          sfor<0, H>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            acc[i] |= (g0[i] & mask0) | (g1[i] & mask1);
+          });
+        }
+        st_rows<H>(ws, dst + blk * H, acc);
+      }
+      if (kind == kLoadSel) continue;
+    } else if (kind == kMulR2) {
+      copy_rows<H>(ws, Lay::B, cr2, 0, n);
+    } else if (kind == kMulG1) {
+      copy_rows<H>(ws, Lay::B, ws, Lay::G + n, n);
+    } else if (kind == kMulOne) {
+#pragma nounroll
+      for (uint32_t i = 0; i < n; ++i) ws.st(Lay::B + i, i == 0 ? 1u : 0u);
+    }
+    mont_blk<H, K, TRUNC>(kind == kSqr, ws, cn, cnp);
+    if (store_e >= 0) copy_rows<H>(ws, Lay::G + (uint32_t)store_e * n, ws, Lay::Y, n);
+  }
+  // canonical result: subtract N once if Y >= N (constant time)
+  int64_t br = 0;
+#pragma nounroll
+  for (uint32_t i = 0; i < n; ++i) {
+    const int64_t v = (int64_t)ws.ld(Lay::Y + i) - (int64_t)cn.ld(i) + br;
+    ws.st(Lay::B + i, (uint32_t)v & kLimbMask);
+    br = v >> kLimbBits;
+  }
+  const uint32_t src = br != 0 ? Lay::Y : Lay::B;
+  if (live) contract_rows<H, K>(ws, src, out + (size_t)inst * bw, bw);
+}
+
+}  // namespace mx

@@ -1,6 +1,8 @@
 // Per-size-class instantiation of the kernels.  Built once per class with
 // -DMX_CLASS_BITS=<bits>; each object exports mx::class_ops_<bits>().
-#include "mx_kernels.hpp"
+// Classes up to 2048 bits use the register-resident kernels (mx_kernels.hpp);
+// larger classes use the block-level schoolbook (mx_block.hpp).
+#include "mx_block.hpp"
 
 #ifndef MX_CLASS_BITS
 #error "MX_CLASS_BITS must be defined"
@@ -10,9 +12,14 @@ namespace mx {
 namespace {
 
 constexpr int kBits = MX_CLASS_BITS;
-constexpr int kN = limbs_for(kBits);
-constexpr int kW = words_for(kBits);        // canonical values (< N)
-constexpr int kRW = words_for(28 * kN);     // Montgomery-domain values (< 2N < R)
+constexpr bool kBlock = kBits > 2048;
+constexpr int kH = 37;                                    // block limbs (block classes)
+constexpr int kK = (limbs_for(kBits) + kH - 1) / kH;      // blocks (block classes)
+constexpr int kN = kBlock ? kH * kK : limbs_for(kBits);   // limbs, R = 2^(28 kN)
+constexpr int kW = words_for(kBits);                      // canonical values (< N)
+constexpr int kRW = words_for(28 * kN);                   // Montgomery-domain values (< 2N < R)
+
+static_assert(!kBlock || (kK >= 2 && kK <= 4), "block classes: redundant limbs need K <= 4");
 
 hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
   const uint32_t blocks = (ctx.count + 63) / 64;
@@ -20,39 +27,66 @@ hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
   return hipGetLastError();
 }
 
+// per-lane workspace words: block classes keep Y, B, T, Q, S (and the table)
+// in memory; register-resident classes need only the exponentiation table
+uint32_t ws_rows_fn(bool modexp, uint32_t w) {
+  if (kBlock) return modexp ? BlkLayout<kH, kK>::rows(w) : BlkLayout<kH, kK>::G;
+  return modexp ? (1u << w) * (uint32_t)kN : 0u;
+}
+
 hipError_t mont_fn(bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
-                   const uint64_t* b, uint64_t* out, uint32_t count, hipStream_t st) {
+                   const uint64_t* b, uint64_t* out, uint32_t count, uint32_t* ws, uint32_t tstride,
+                   uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
   const uint32_t blocks = (count + 63) / 64;
-  if (trunc) {
-    if (sqr)
-      hipLaunchKernelGGL((k_mont<kN, kRW, true, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count);
-    else
-      hipLaunchKernelGGL((k_mont<kN, kRW, true, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count);
+  if constexpr (kBlock) {
+#define MX_L(T, S)                                                                                              \
+  hipLaunchKernelGGL((k_mont_blk<kH, kK, T, S>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count, ws, \
+                     tstride, ws_bytes, coff)
+    if (trunc) {
+      if (sqr) MX_L(true, true); else MX_L(true, false);
+    } else {
+      if (sqr) MX_L(false, true); else MX_L(false, false);
+    }
+#undef MX_L
   } else {
-    if (sqr)
-      hipLaunchKernelGGL((k_mont<kN, kRW, false, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count);
-    else
-      hipLaunchKernelGGL((k_mont<kN, kRW, false, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count);
+    (void)ws;
+    (void)tstride;
+    (void)ws_bytes;
+#define MX_L(T, S) \
+  hipLaunchKernelGGL((k_mont<kN, kRW, T, S>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count, coff)
+    if (trunc) {
+      if (sqr) MX_L(true, true); else MX_L(true, false);
+    } else {
+      if (sqr) MX_L(false, true); else MX_L(false, false);
+    }
+#undef MX_L
   }
   return hipGetLastError();
 }
 
 hipError_t modexp_fn(bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base, const uint64_t* ex,
-                     uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out, uint32_t count, uint32_t* table,
-                     uint32_t tstride, uint32_t coff, hipStream_t st) {
+                     uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out, uint32_t count, uint32_t* ws,
+                     uint32_t tstride, uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
   const uint32_t blocks = (count + 63) / 64;
-  const size_t tbytes = ((size_t)1 << w) * kN * tstride * sizeof(uint32_t);
-  if (tbytes > 0x7FFFFFFFull) return hipErrorInvalidValue;  // one buffer descriptor spans < 2 GiB
-  if (trunc)
-    hipLaunchKernelGGL((k_modexp<kN, kW, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits, ewords, w,
-                       out, count, table, tstride, (uint32_t)tbytes, coff);
-  else
-    hipLaunchKernelGGL((k_modexp<kN, kW, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits, ewords,
-                       w, out, count, table, tstride, (uint32_t)tbytes, coff);
+  if constexpr (kBlock) {
+    if (trunc)
+      hipLaunchKernelGGL((k_modexp_blk<kH, kK, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
+                         ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+    else
+      hipLaunchKernelGGL((k_modexp_blk<kH, kK, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
+                         ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+  } else {
+    if (trunc)
+      hipLaunchKernelGGL((k_modexp<kN, kW, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits, ewords,
+                         w, out, count, ws, tstride, ws_bytes, coff);
+    else
+      hipLaunchKernelGGL((k_modexp<kN, kW, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
+                         ewords, w, out, count, ws, tstride, ws_bytes, coff);
+  }
   return hipGetLastError();
 }
 
-const ClassOps kOps = {kBits, kN, ctx_fn, mont_fn, modexp_fn};
+const ClassOps kOps = {kBits, kN, ctx_fn, ws_rows_fn, mont_fn, modexp_fn};
 
 }  // namespace
 

@@ -226,6 +226,37 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
   c[N - 1] = (uint32_t)(carry + t[2 * N - 1]);
 }
 
+// ---- block routines for the block-level schoolbook (large size classes) ---
+
+// r = a * b mod 2^(28 H): the low half of the product (Algorithm 6 step 1 on a block).
+template <int H>
+__device__ __forceinline__ void lo_sb(const uint32_t (&a)[H], const uint32_t (&b)[H], uint32_t (&r)[H]) {
+  uint64_t carry = 0;
+  sfor<0, H>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    uint64_t acc = colsum<k, 0, k>(a, b) + carry;
+    r[k] = (uint32_t)acc & kLimbMask;
+    carry = acc >> kLimbBits;
+  });
+}
+
+// v = sum over the partial products a_i b_j with i + j >= H - 2 of
+// a_i b_j 2^(28 (i + j - H + 2)), normalised to H + 2 limbs: the partial
+// products of Theorem 2 that a block contributes at or above column n - 2.
+template <int H>
+__device__ __forceinline__ void hi_sb(const uint32_t (&a)[H], const uint32_t (&b)[H], uint32_t (&v)[H + 2]) {
+  uint64_t carry = 0;
+  sfor<H - 2, 2 * H - 1>([&](auto W) {
+    constexpr int w = decltype(W)::value;
+    constexpr int lo = w > H - 1 ? w - (H - 1) : 0;
+    constexpr int hi = w < H - 1 ? w : H - 1;
+    uint64_t acc = colsum<w, lo, hi>(a, b) + carry;
+    v[w - (H - 2)] = (uint32_t)acc & kLimbMask;
+    carry = acc >> kLimbBits;
+  });
+  v[H + 1] = (uint32_t)carry;
+}
+
 // ---- layout: 64-bit words <-> 28-bit limbs (expand / contract, Section 6) -
 
 // x = the low 28 N bits of the W-word little-endian value at src.

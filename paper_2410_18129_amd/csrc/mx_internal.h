@@ -17,22 +17,28 @@ struct CtxDev {
 };
 
 // Launchers of one size class (one instantiation of the kernel templates).
+// Workspace: ws_rows(modexp, w) 32-bit words per instance, laid out limb-major
+// with `tstride` instances per row (ws_bytes = rows * tstride * 4 < 2 GiB);
+// `coff` is added to the instance index to find its context when cidx is NULL.
 struct ClassOps {
   int bits;
   int limbs;
   hipError_t (*ctx_init)(const uint64_t* mods, const CtxDev& ctx, hipStream_t st);
+  uint32_t (*ws_rows)(bool modexp, uint32_t w);
   hipError_t (*mont)(bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
-                     const uint64_t* b, uint64_t* out, uint32_t count, hipStream_t st);
+                     const uint64_t* b, uint64_t* out, uint32_t count, uint32_t* ws, uint32_t tstride,
+                     uint32_t ws_bytes, uint32_t coff, hipStream_t st);
   hipError_t (*modexp)(bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
                        const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out,
-                       uint32_t count, uint32_t* table, uint32_t tstride, uint32_t coff, hipStream_t st);
+                       uint32_t count, uint32_t* ws, uint32_t tstride, uint32_t ws_bytes, uint32_t coff,
+                       hipStream_t st);
 };
 
-// Largest table one launch may use: a buffer descriptor spans < 2 GiB.
-constexpr size_t kMaxTableBytes = 0x7FFFFFFFull;
+// Largest workspace one launch may use: a buffer descriptor spans < 2 GiB.
+constexpr size_t kMaxWsBytes = 0x7FFFFFFFull;
 
 // Size classes built into the library.
-#define MX_FOR_EACH_CLASS(X) X(64) X(128) X(256) X(512) X(1024) X(2048)
+#define MX_FOR_EACH_CLASS(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(3072) X(4096)
 
 #define MX_DECL_CLASS(B) const ClassOps* class_ops_##B();
 MX_FOR_EACH_CLASS(MX_DECL_CLASS)

@@ -36,72 +36,72 @@ __device__ __forceinline__ void stage_ctx(uint32_t* s_ctx, const uint32_t* cn, c
 
 // ---- context: N, N' = -N^{-1} mod R, R mod N, R^2 mod N (Section 4) -------
 //
-// N' by Newton lifting y <- y (2 - N y) mod R from y = N (N^2 = 1 mod 8),
-// tripling... doubling the number of correct low bits per step; R mod N and
-// R^2 mod N by 28n + 28n constant-time doublings with a conditional subtract.
+// N' digit by digit: q_i = acc_0 * (-N_0^{-1}) mod 2^28 with acc += q_i N and a
+// one-limb shift per digit (the q of the Montgomery reduction of 1, taken
+// limb-serially; acc keeps only the limbs still below R).  R mod N and
+// R^2 mod N start from 2^(t-1) <= N (t = bit length of N) and double with a
+// conditional subtraction until 2^(28 n) and 2^(56 n).
 template <int N, int W>
 __global__ void __launch_bounds__(64) k_ctx_init(const uint64_t* __restrict__ mods, CtxDev ctx) {
   const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
   if (gid >= ctx.count) return;
   uint32_t m[N];
   expand<N, W>(mods + (size_t)gid * W, m);
+  const size_t cs = ctx.stride;
+#pragma unroll 1
+  for (int i = 0; i < N; ++i) ctx.n[(size_t)i * cs + gid] = m[i];
 
-  uint32_t y[N];
-  sfor<0, N>([&](auto I) { y[decltype(I)::value] = m[decltype(I)::value]; });
-  // correct bits: 3 * 2^it >= 28 N  <=>  it >= log2(28 N / 3); 12 covers N <= 438
-#pragma nounroll
-  for (int it = 0; it < 12; ++it) {
-    uint32_t t[2 * N];
-    mul_sb<N>(m, y, t);  // low N limbs: N y mod R
-    uint32_t u[N];
-    uint32_t cy = 3;  // (R - 1 - x) + 3 = 2 - x mod R
-    sfor<0, N>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      uint32_t v = (~t[i] & kLimbMask) + cy;
-      u[i] = v & kLimbMask;
-      cy = v >> kLimbBits;
-    });
-    mul_sb<N>(y, u, t);
-    sfor<0, N>([&](auto I) { y[decltype(I)::value] = t[decltype(I)::value]; });
-  }
-  uint32_t np[N];
+  // -N_0^{-1} mod 2^28 by Newton's iteration on 32-bit words (3 -> 96 bits)
+  uint32_t inv = m[0];
+  for (int it = 0; it < 5; ++it) inv *= 2u - m[0] * inv;
+  const uint32_t n0p = (0u - inv) & kLimbMask;
   {
-    uint32_t cy = 1;  // -y mod R = (R - 1 - y) + 1
-    sfor<0, N>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      uint32_t v = (~y[i] & kLimbMask) + cy;
-      np[i] = v & kLimbMask;
-      cy = v >> kLimbBits;
-    });
+    uint32_t acc[N];  // acc[j] is limb i + j of 1 + (q_0 .. q_{i-1}) N
+    sfor<0, N>([&](auto J) { acc[decltype(J)::value] = decltype(J)::value == 0 ? 1u : 0u; });
+#pragma unroll 1
+    for (int i = 0; i < N; ++i) {
+      const uint32_t qi = (uint32_t)(((uint64_t)acc[0] * n0p) & kLimbMask);
+      ctx.np[(size_t)i * cs + gid] = qi;
+      uint64_t carry = 0;
+      sfor<0, N>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        const uint64_t v = (uint64_t)acc[j] + (uint64_t)qi * m[j] + carry;
+        acc[j] = (uint32_t)v & kLimbMask;
+        carry = v >> kLimbBits;
+      });
+      sfor<0, N - 1>([&](auto J) { acc[decltype(J)::value] = acc[decltype(J)::value + 1]; });
+      acc[N - 1] = 0;
+    }
   }
-
+  uint32_t t = 0;  // bit length of N
+  sfor<0, N>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    if (m[i]) t = kLimbBits * i + (32u - __clz(m[i]));
+  });
   uint32_t r[N];
-  sfor<0, N>([&](auto I) { r[decltype(I)::value] = 0; });
-  r[0] = 1;
-  uint32_t r1[N];
-#pragma nounroll
-  for (int s = 0; s < 2 * kLimbBits * N; ++s) {
+  sfor<0, N>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    r[i] = (uint32_t)i == (t - 1) / kLimbBits ? 1u << ((t - 1) % kLimbBits) : 0u;
+  });
+  const uint32_t total = 2u * kLimbBits * N - (t - 1);
+#pragma unroll 1
+  for (uint32_t s = 0; s < total; ++s) {
     // r = 2 r (r < N <= R/4 so no limb overflows), then subtract N if r >= N
     uint32_t top = 0;
     sfor<0, N>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      uint32_t v = (r[i] << 1) | top;
+      const uint32_t v = (r[i] << 1) | top;
       top = r[i] >> (kLimbBits - 1);
       r[i] = v & kLimbMask;
     });
     canon<N>(r, m);
-    if (s == kLimbBits * N - 1) {
-      sfor<0, N>([&](auto I) { r1[decltype(I)::value] = r[decltype(I)::value]; });
+    if (s + t == (uint32_t)(kLimbBits * N)) {  // r = 2^(t - 1 + s + 1) = R mod N
+#pragma unroll 1
+      for (int i = 0; i < N; ++i) ctx.r1[(size_t)i * cs + gid] = r[i];
     }
   }
-  sfor<0, N>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    const size_t o = (size_t)i * ctx.stride + gid;
-    ctx.n[o] = m[i];
-    ctx.np[o] = np[i];
-    ctx.r1[o] = r1[i];
-    ctx.r2[o] = r[i];
-  });
+#pragma unroll 1
+  for (int i = 0; i < N; ++i) ctx.r2[(size_t)i * cs + gid] = r[i];
 }
 
 // ---- batched modmul / modsqr ---------------------------------------------
@@ -109,11 +109,11 @@ __global__ void __launch_bounds__(64) k_ctx_init(const uint64_t* __restrict__ mo
 template <int N, int RW, bool TRUNC, bool SQR>
 __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                              const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
-                                             uint64_t* __restrict__ out, uint32_t count) {
+                                             uint64_t* __restrict__ out, uint32_t count, uint32_t coff) {
   const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
   const bool live = gid < count;
   const uint32_t inst = live ? gid : count - 1;
-  uint32_t c = cidx ? cidx[inst] : inst;
+  uint32_t c = cidx ? cidx[inst] : inst + coff;
   c = c < ctx.count ? c : 0u;
   const uint32_t* cn = ctx.n + c;
   const uint32_t* cnp = ctx.np + c;

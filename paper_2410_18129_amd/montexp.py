@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libmontexp.so")
 
 MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EUNSUPPORTED = 0, 1, 2, 3, 4
 MX_REDC_TRUNC, MX_REDC_PLAIN = 0, 1
-SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048)
+SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
 # exported symbols and their ctypes signatures (mirrors include/montexp.h)
@@ -70,8 +70,14 @@ def words_for(bits):
     return (bits + 63) // 64
 
 
+BLOCK_LIMBS = 37  # classes above 2048 bits use whole 37-limb blocks
+
+
 def limbs_for(bits):
-    return (bits + 2 + LIMB_BITS - 1) // LIMB_BITS
+    n = (bits + 2 + LIMB_BITS - 1) // LIMB_BITS
+    if bits > 2048:
+        n = BLOCK_LIMBS * ((n + BLOCK_LIMBS - 1) // BLOCK_LIMBS)
+    return n
 
 
 def r_bits_for(bits):

@@ -7,7 +7,10 @@ LIMB = 28
 
 
 def r_bits(bits):
-    return LIMB * ((bits + 2 + LIMB - 1) // LIMB)
+    n = (bits + 2 + LIMB - 1) // LIMB
+    if bits > 2048:  # whole 37-limb blocks
+        n = 37 * ((n + 36) // 37)
+    return LIMB * n
 
 
 def ints_dev(vals, words, device="cuda"):

@@ -14,7 +14,7 @@ from tests.gpu_util import adversarial_pairs, dev_ints, ints_dev, r_bits
 
 pytestmark = pytest.mark.gpu
 
-CLASSES = (64, 128, 256, 512, 1024, 2048)
+CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 
 
 @pytest.fixture(scope="module")
@@ -117,7 +117,8 @@ def test_mont_ctx_idx_indirection(mx):
     ctx.close()
 
 
-@pytest.mark.parametrize("bits,window", [(64, 1), (64, 3), (128, 4), (256, 2), (512, 4), (1024, 5), (2048, 5)])
+@pytest.mark.parametrize("bits,window", [(64, 1), (64, 3), (128, 4), (256, 2), (512, 4), (1024, 5), (2048, 5),
+                                         (2048, 3), (3072, 5), (4096, 6)])
 def test_modexp_random(mx, bits, window):
     count = 8 if bits >= 1024 else 70
     g = wl.stream(6, "bases")
@@ -132,7 +133,7 @@ def test_modexp_random(mx, bits, window):
     for plain in (False, True):
         res[plain] = dev_ints(mx.modexp(ctx, bd, ed, bits, window=window, plain=plain))
     assert res[False] == res[True]
-    check = range(count) if bits <= 1024 else range(3)
+    check = range(count) if bits <= 1024 else range(3 if bits <= 2048 else 1)
     for i in check:
         assert res[False][i] == oracle.modexp(base[i], exps[i], Ns[i], bits), i
     ctx.close()
