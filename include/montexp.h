@@ -14,10 +14,11 @@
  *  - Operand pointers are DEVICE pointers unless the name says _host.
  *    `stream` is a hipStream_t (NULL = the default stream).  Batch calls
  *    only enqueue work: results are valid after the stream synchronises.
- *  - Size classes: bits in {64, 128, 256, 512, 1024, 2048}.  A class uses
- *    n = ceil((bits + 2) / 28) limbs of 28 bits and R = 2^(28 n) >= 4 * 2^bits
- *    (r_bits = 28 n, reported by mont_ctx_query), so products of values below
- *    2N reduce to values below 2N with no final subtraction (Section 4).
+ *  - Size classes: bits in {64, 128, 256, 512, 1024, 2048, 3072, 4096}.  A
+ *    class uses n limbs of 28 bits, n = ceil((bits + 2) / 28) rounded up to a
+ *    multiple of 37 above 2048 bits, and R = 2^(28 n) >= 4 * 2^bits (r_bits =
+ *    28 n, reported by mont_ctx_query), so products of values below 2N reduce
+ *    to values below 2N with no final subtraction (Section 4).
  *  - Canonical values (< N) use words = ceil(bits / 64); Montgomery-domain
  *    values (< 2N) use mont_words = ceil(r_bits / 64).
  *  - The caller owns all operand buffers and the stream; the library owns
@@ -49,10 +50,13 @@ typedef enum {
   MX_EUNSUPPORTED = 4
 } mx_status;
 
-/* flags for the batch calls */
+/* flags for the batch calls (OR-ed) */
 enum {
   MX_REDC_TRUNC = 0, /* truncated reduction, Section 5 Algorithm 6 (default)  */
-  MX_REDC_PLAIN = 1  /* full q*N product, Section 4 Algorithm 3 (B_fma)        */
+  MX_REDC_PLAIN = 1, /* full q*N product, Section 4 Algorithm 3 (B_fma)        */
+  MX_IMPL_BLOCK = 2  /* block-level schoolbook over 37-limb blocks for the
+                        1024/2048 classes (the only kernels above 2048 bits);
+                        same results, MX_EUNSUPPORTED where not built        */
 };
 
 /* Montgomery contexts for `count` moduli of size class `bits` (Section 4:
@@ -102,6 +106,59 @@ mx_status mont_sqr_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uin
 mx_status modexp_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint64_t *base, const uint64_t *exp,
                        uint32_t exp_bits, uint32_t window, uint64_t *out, uint32_t n, uint32_t flags,
                        void *stream);
+
+/* ---- mixed sizes in one persistent launch ----------------------------------
+ * For callers that hold batches of several size classes at once (not a
+ * construct of the paper, which exponentiates one size per call): the
+ * instances of all batches are cut into 64-instance tiles, ordered by
+ * decreasing cost and consumed by one persistent grid (one wavefront per
+ * SIMD) through a device work counter.  The truncated reduction is used.
+ * Supported classes: 1024, 2048 (optionally MX_IMPL_BLOCK), 3072, 4096. */
+typedef struct mx_batch_desc {
+  const mont_ctx *ctx;      /* contexts of this batch's class                         */
+  const uint32_t *ctx_idx;  /* device, n entries, or NULL: instance i uses context i  */
+  const uint64_t *base;     /* device, n x ceil(bits/64) words, base < N              */
+  const uint64_t *exp;      /* device, n x ceil(exp_bits/64) words                    */
+  uint64_t *out;            /* device, n x ceil(bits/64) words                        */
+  uint32_t n;
+  uint32_t exp_bits;
+  uint32_t window;          /* 1..8, 0 = library choice                               */
+  uint32_t flags;           /* 0 or MX_IMPL_BLOCK                                     */
+  float tile_cost;          /* relative cost of one 64-instance tile, 0 = estimate    */
+} mx_batch_desc;
+
+typedef struct mx_mixed_plan mx_mixed_plan;
+
+/* Validates the batches and allocates the job list, the work counter and one
+ * workspace slot per persistent wave and batch (2^w r_bits/8 bytes per lane,
+ * plus the working arrays of the block kernels).  The descriptors' device
+ * pointers are captured: every launch of the plan reads and writes them.
+ * MX_EUNSUPPORTED if a batch's workspace would exceed 2 GiB (smaller window). */
+mx_status mx_mixed_plan_create(mx_mixed_plan **out, const mx_batch_desc *batches, uint32_t nbatch);
+
+/* Enqueues a counter-reset kernel and the persistent kernel on `stream`.
+ * Allocates nothing.  Launches of one plan must not overlap. */
+mx_status mx_mixed_plan_launch(mx_mixed_plan *plan, void *stream);
+
+/* As mx_mixed_plan_launch, through a HIP graph captured on the first call
+ * and replayed afterwards. */
+mx_status mx_mixed_plan_launch_graph(mx_mixed_plan *plan, void *stream);
+
+/* Job (tile) count, persistent waves, and the window chosen for each batch. */
+mx_status mx_mixed_plan_query(const mx_mixed_plan *plan, uint32_t *njobs, uint32_t *nslots, uint32_t *windows);
+
+/* Frees the plan (after its launches have completed). */
+void mx_mixed_plan_destroy(mx_mixed_plan *plan);
+
+/* ---- autotuning --------------------------------------------------------------
+ * Times modexp_batch on n seeded sample instances of ctx (bases below
+ * 2^(bits-1), uniform exp_bits-bit exponents) for each candidate window, and
+ * for the block kernels too when try_block and the class has them; returns
+ * the fastest window and flags, and its time per 64-instance tile (the best
+ * of `reps` runs, in ms).  Allocates its sample buffers. */
+mx_status mx_tune_modexp(const mont_ctx *ctx, uint32_t n, uint32_t exp_bits, const uint32_t *windows,
+                         uint32_t nwin, uint32_t try_block, uint32_t reps, uint32_t *best_window,
+                         uint32_t *best_flags, float *best_ms, void *stream);
 
 /* Thread-local message for the last non-OK status of this thread. */
 const char *mont_last_error(void);

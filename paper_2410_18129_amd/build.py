@@ -37,6 +37,8 @@ def build(jobs=None, only=None, verbose=True):
     classes = CLASSES if not only else tuple(c for c in CLASSES if c in only)
     units = [("mx_abi", [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, "mx_abi.hip"),
                                           "-o", os.path.join(BUILD, "mx_abi.o")])]
+    units.append(("mx_mixed", [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, "mx_mixed.hip"),
+                                                "-o", os.path.join(BUILD, "mx_mixed.o")]))
     for b in classes:
         units.append(("class_%d" % b, [HIPCC] + FLAGS + ["-DMX_CLASS_BITS=%d" % b, "-c",
                                                        os.path.join(CSRC, "mx_class.hip"),
@@ -44,14 +46,15 @@ def build(jobs=None, only=None, verbose=True):
     jobs = jobs or min(len(units), max(1, os.cpu_count() or 1))
     t0 = time.time()
     # largest classes first so they overlap with the small ones
-    units.sort(key=lambda u: -int(u[0].split("_")[1]) if u[0].startswith("class") else 0)
+    units.sort(key=lambda u: -int(u[0].split("_")[1]) if u[0].startswith("class") else
+               (-4096 if u[0] == "mx_mixed" else 0))
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = {ex.submit(_run, cmd): name for name, cmd in units}
         for f in cf.as_completed(futs):
             dt = f.result()
             if verbose:
                 print("  built %-10s %6.1fs" % (futs[f], dt), flush=True)
-    objs = [os.path.join(BUILD, "mx_abi.o")] + [os.path.join(BUILD, "mx_class_%d.o" % b) for b in CLASSES]
+    objs = [os.path.join(BUILD, "mx_abi.o"), os.path.join(BUILD, "mx_mixed.o")] + [os.path.join(BUILD, "mx_class_%d.o" % b) for b in CLASSES]
     missing = [o for o in objs if not os.path.exists(o)]
     if missing:
         raise RuntimeError("missing objects (build the other classes first): %s" % missing)

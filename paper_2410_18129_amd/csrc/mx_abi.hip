@@ -10,6 +10,7 @@
 
 #include "../../include/montexp.h"
 #include "mx_internal.h"
+#include "mx_ctx.h"
 
 namespace {
 
@@ -57,20 +58,15 @@ struct DeviceGuard {
 
 }  // namespace
 
-struct mont_ctx {
-  const mx::ClassOps* ops = nullptr;
-  uint32_t bits = 0;
-  uint32_t limbs = 0;
-  uint32_t count = 0;
-  int device = 0;
-  mx::CtxDev dev{};
-  void* mem = nullptr;
-  size_t bytes = 0;
-  // exponentiation workspace owned by the context (grow-only)
-  std::mutex ws_mu;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-};
+mx_status mx_fail(mx_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+
 
 // Grows the context's workspace to at least `need` bytes (caller holds ws_mu).
 static mx_status ensure_ws(mont_ctx* ctx, size_t need, const char* name) {
@@ -211,12 +207,16 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!a || !out || (!sqr && !b)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)MX_REDC_PLAIN) return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK))
+    return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
+  const int impl = (flags & MX_IMPL_BLOCK) ? 1 : 0;
+  if (impl && !ctx->ops->has_block)
+    return fail(MX_EUNSUPPORTED, "%s: no block kernels for the %u-bit class", name, ctx->bits);
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
   mont_ctx* mctx = const_cast<mont_ctx*>(ctx);
-  const uint32_t rows = ctx->ops->ws_rows(false, 0);
+  const uint32_t rows = ctx->ops->ws_rows(impl, false, 0);
   const uint32_t chunk = chunk_for(rows, n);
   if (chunk == 0) return fail(MX_EUNSUPPORTED, "%s: workspace row too large", name);
   const uint32_t tstride = round_up(chunk, 64);
@@ -227,7 +227,7 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   const uint32_t mw = words_for(28 * ctx->limbs);
   for (uint32_t off = 0; off < n; off += chunk) {
     const uint32_t cnt = n - off < chunk ? n - off : chunk;
-    hipError_t e = ctx->ops->mont(!(flags & MX_REDC_PLAIN), sqr, ctx->dev, ctx_idx ? ctx_idx + off : nullptr,
+    hipError_t e = ctx->ops->mont(impl, !(flags & MX_REDC_PLAIN), sqr, ctx->dev, ctx_idx ? ctx_idx + off : nullptr,
                                   a + (size_t)off * mw, b + (size_t)off * mw, out + (size_t)off * mw, cnt,
                                   (uint32_t*)mctx->ws, tstride, (uint32_t)need, ctx_idx ? 0u : off,
                                   (hipStream_t)stream);
@@ -253,13 +253,17 @@ mx_status modexp_batch(const mont_ctx* cctx, const uint32_t* ctx_idx, const uint
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!base || !out || (exp_bits && !exp)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)MX_REDC_PLAIN) return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK))
+    return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
+  const int impl = (flags & MX_IMPL_BLOCK) ? 1 : 0;
+  if (impl && !ctx->ops->has_block)
+    return fail(MX_EUNSUPPORTED, "%s: no block kernels for the %u-bit class", name, ctx->bits);
   if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   const uint32_t w = window ? window : default_window(ctx->bits);
   const uint32_t ewords = (exp_bits + 63) / 64;
   const uint32_t W = words_for(ctx->bits);
-  const uint32_t rows = ctx->ops->ws_rows(true, w);
+  const uint32_t rows = ctx->ops->ws_rows(impl, true, w);
   const uint32_t chunk = chunk_for(rows, n);
   if (chunk == 0) return fail(MX_EUNSUPPORTED, "%s: window %u too large for this size class", name, w);
   const uint32_t tstride = round_up(chunk, 64);
@@ -272,7 +276,7 @@ mx_status modexp_batch(const mont_ctx* cctx, const uint32_t* ctx_idx, const uint
   const bool trunc = !(flags & MX_REDC_PLAIN);
   for (uint32_t off = 0; off < n; off += chunk) {
     const uint32_t cnt = n - off < chunk ? n - off : chunk;
-    hipError_t e = ctx->ops->modexp(trunc, ctx->dev, ctx_idx ? ctx_idx + off : nullptr, base + (size_t)off * W,
+    hipError_t e = ctx->ops->modexp(impl, trunc, ctx->dev, ctx_idx ? ctx_idx + off : nullptr, base + (size_t)off * W,
                                     exp_bits ? exp + (size_t)off * ewords : exp, exp_bits, ewords, w,
                                     out + (size_t)off * W, cnt, (uint32_t*)ctx->ws, tstride, (uint32_t)need,
                                     ctx_idx ? 0u : off, (hipStream_t)stream);

@@ -257,19 +257,20 @@ __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __r
 
 // ---- modexp, block version (same schedule as k_modexp) ----------------------
 template <int H, int K, bool TRUNC>
-__global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
-                                                   const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
-                                                   uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
-                                                   uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
-                                                   uint32_t tstride, uint32_t ws_bytes, uint32_t coff) {
+__device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
+                                                const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
+                                                uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
+                                                uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
+                                                uint32_t tstride, uint32_t ws_bytes, uint32_t coff, uint32_t tile0,
+                                                uint32_t wcol) {
   using Lay = BlkLayout<H, K>;
   constexpr uint32_t n = Lay::n;
-  const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
+  const uint32_t gid = tile0 + (threadIdx.x & 63u);
   const bool live = gid < count;
   const uint32_t inst = live ? gid : count - 1;
   uint32_t c = cidx ? cidx[inst] : inst + coff;
   c = c < ctx.count ? c : 0u;
-  const LaneBuf ws{make_buf(ws_base, ws_bytes), gid * 4u, tstride * 4u};
+  const LaneBuf ws{make_buf(ws_base, ws_bytes), wcol * 4u, tstride * 4u};
   const uint32_t cbytes = n * ctx.stride * 4u;
   const LaneBuf cn{make_buf(ctx.n, cbytes), c * 4u, ctx.stride * 4u};
   const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
@@ -353,6 +354,17 @@ __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* _
   }
   const uint32_t src = br != 0 ? Lay::Y : Lay::B;
   if (live) contract_rows<H, K>(ws, src, out + (size_t)inst * bw, bw);
+}
+
+template <int H, int K, bool TRUNC>
+__global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
+                                                   const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
+                                                   uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
+                                                   uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
+                                                   uint32_t tstride, uint32_t ws_bytes, uint32_t coff) {
+  const uint32_t tile0 = blockIdx.x * 64;
+  modexp_tile_blk<H, K, TRUNC>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count, ws_base, tstride, ws_bytes,
+                               coff, tile0, tile0 + (threadIdx.x & 63u));
 }
 
 }  // namespace mx

@@ -12,14 +12,15 @@ namespace mx {
 namespace {
 
 constexpr int kBits = MX_CLASS_BITS;
-constexpr bool kBlock = kBits > 2048;
-constexpr int kH = 37;                                    // block limbs (block classes)
-constexpr int kK = (limbs_for(kBits) + kH - 1) / kH;      // blocks (block classes)
+constexpr bool kBlock = kBits > 2048;                     // only the block kernels exist
+constexpr int kH = 37;                                    // block limbs
+constexpr int kK = (limbs_for(kBits) + kH - 1) / kH;      // blocks
 constexpr int kN = kBlock ? kH * kK : limbs_for(kBits);   // limbs, R = 2^(28 kN)
+constexpr bool kHasBlk = kN % kH == 0;                    // block kernels also built (same R)
 constexpr int kW = words_for(kBits);                      // canonical values (< N)
 constexpr int kRW = words_for(28 * kN);                   // Montgomery-domain values (< 2N < R)
 
-static_assert(!kBlock || (kK >= 2 && kK <= 4), "block classes: redundant limbs need K <= 4");
+static_assert(!kHasBlk || (kK >= 1 && kK <= 4), "block kernels: redundant limbs need K <= 4");
 
 hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
   const uint32_t blocks = (ctx.count + 63) / 64;
@@ -29,26 +30,31 @@ hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
 
 // per-lane workspace words: block classes keep Y, B, T, Q, S (and the table)
 // in memory; register-resident classes need only the exponentiation table
-uint32_t ws_rows_fn(bool modexp, uint32_t w) {
-  if (kBlock) return modexp ? BlkLayout<kH, kK>::rows(w) : BlkLayout<kH, kK>::G;
+uint32_t ws_rows_fn(int impl, bool modexp, uint32_t w) {
+  if (kBlock || (kHasBlk && impl == 1)) return modexp ? BlkLayout<kH, kK>::rows(w) : BlkLayout<kH, kK>::G;
+  (void)impl;
   return modexp ? (1u << w) * (uint32_t)kN : 0u;
 }
 
-hipError_t mont_fn(bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
+hipError_t mont_fn(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
                    const uint64_t* b, uint64_t* out, uint32_t count, uint32_t* ws, uint32_t tstride,
                    uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
   const uint32_t blocks = (count + 63) / 64;
-  if constexpr (kBlock) {
+  if constexpr (kBlock || kHasBlk) {
+    if (kBlock || impl == 1) {
 #define MX_L(T, S)                                                                                              \
   hipLaunchKernelGGL((k_mont_blk<kH, kK, T, S>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count, ws, \
                      tstride, ws_bytes, coff)
-    if (trunc) {
-      if (sqr) MX_L(true, true); else MX_L(true, false);
-    } else {
-      if (sqr) MX_L(false, true); else MX_L(false, false);
-    }
+      if (trunc) {
+        if (sqr) MX_L(true, true); else MX_L(true, false);
+      } else {
+        if (sqr) MX_L(false, true); else MX_L(false, false);
+      }
 #undef MX_L
-  } else {
+      return hipGetLastError();
+    }
+  }
+  if constexpr (!kBlock) {
     (void)ws;
     (void)tstride;
     (void)ws_bytes;
@@ -64,18 +70,22 @@ hipError_t mont_fn(bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx
   return hipGetLastError();
 }
 
-hipError_t modexp_fn(bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base, const uint64_t* ex,
+hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base, const uint64_t* ex,
                      uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out, uint32_t count, uint32_t* ws,
                      uint32_t tstride, uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
   const uint32_t blocks = (count + 63) / 64;
-  if constexpr (kBlock) {
-    if (trunc)
-      hipLaunchKernelGGL((k_modexp_blk<kH, kK, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
-                         ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
-    else
-      hipLaunchKernelGGL((k_modexp_blk<kH, kK, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
-                         ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
-  } else {
+  if constexpr (kBlock || kHasBlk) {
+    if (kBlock || impl == 1) {
+      if (trunc)
+        hipLaunchKernelGGL((k_modexp_blk<kH, kK, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
+                           ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+      else
+        hipLaunchKernelGGL((k_modexp_blk<kH, kK, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex,
+                           ebits, ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (!kBlock) {
     if (trunc)
       hipLaunchKernelGGL((k_modexp<kN, kW, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits, ewords,
                          w, out, count, ws, tstride, ws_bytes, coff);
@@ -86,7 +96,7 @@ hipError_t modexp_fn(bool trunc, const CtxDev& ctx, const uint32_t* cidx, const 
   return hipGetLastError();
 }
 
-const ClassOps kOps = {kBits, kN, ctx_fn, ws_rows_fn, mont_fn, modexp_fn};
+const ClassOps kOps = {kBits, kN, kHasBlk, ctx_fn, ws_rows_fn, mont_fn, modexp_fn};
 
 }  // namespace
 

@@ -20,15 +20,18 @@ struct CtxDev {
 // Workspace: ws_rows(modexp, w) 32-bit words per instance, laid out limb-major
 // with `tstride` instances per row (ws_bytes = rows * tstride * 4 < 2 GiB);
 // `coff` is added to the instance index to find its context when cidx is NULL.
+// impl: 0 = the class's default kernels, 1 = block-level schoolbook over
+// 37-limb blocks (available when has_block; the default above 2048 bits).
 struct ClassOps {
   int bits;
   int limbs;
+  bool has_block;
   hipError_t (*ctx_init)(const uint64_t* mods, const CtxDev& ctx, hipStream_t st);
-  uint32_t (*ws_rows)(bool modexp, uint32_t w);
-  hipError_t (*mont)(bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
+  uint32_t (*ws_rows)(int impl, bool modexp, uint32_t w);
+  hipError_t (*mont)(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
                      const uint64_t* b, uint64_t* out, uint32_t count, uint32_t* ws, uint32_t tstride,
                      uint32_t ws_bytes, uint32_t coff, hipStream_t st);
-  hipError_t (*modexp)(bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
+  hipError_t (*modexp)(int impl, bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
                        const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out,
                        uint32_t count, uint32_t* ws, uint32_t tstride, uint32_t ws_bytes, uint32_t coff,
                        hipStream_t st);

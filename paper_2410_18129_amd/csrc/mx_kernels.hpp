@@ -27,10 +27,11 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t v, uin
 // Copies this lane's N and N' limbs into its LDS column ([limb][lane]).  Each
 // lane reads back only its own column, so no barrier is needed.
 template <int N>
-__device__ __forceinline__ void stage_ctx(uint32_t* s_ctx, const uint32_t* cn, const uint32_t* cnp, size_t cs) {
+__device__ __forceinline__ void stage_ctx(uint32_t* s_ctx, const uint32_t* cn, const uint32_t* cnp, size_t cs,
+                                          uint32_t lane) {
   for (int i = 0; i < N; ++i) {
-    s_ctx[i * 64 + threadIdx.x] = cn[(size_t)i * cs];
-    s_ctx[(N + i) * 64 + threadIdx.x] = cnp[(size_t)i * cs];
+    s_ctx[i * 64 + lane] = cn[(size_t)i * cs];
+    s_ctx[(N + i) * 64 + lane] = cnp[(size_t)i * cs];
   }
 }
 
@@ -120,7 +121,7 @@ __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restr
   const size_t cs = ctx.stride;
 
   __shared__ uint32_t s_ctx[2 * N * 64];
-  stage_ctx<N>(s_ctx, cn, cnp, cs);
+  stage_ctx<N>(s_ctx, cn, cnp, cs, threadIdx.x);
 
   uint32_t x[N];
   expand<N, RW>(a + (size_t)inst * RW, x);
@@ -151,14 +152,20 @@ __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restr
 // multiplication code and the reduction each exist once in the binary.
 enum StepKind : int { kSqr = 0, kMulR2 = 1, kMulG1 = 2, kMulSel = 3, kMulOne = 4, kLoadSel = 5 };
 
+// Modular exponentiation of one tile of 64 instances (one wavefront).
+// tile0: first instance of the tile; lane l handles instance tile0 + l (the
+// lanes past `count` recompute the last instance and store nothing).
+// wcol: this lane's column in the workspace (table rows of tstride columns).
+// s_ctx: 2 N 64 words of LDS for the lane's N and N'.
 template <int N, int BW, bool TRUNC>
-__global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __restrict__ cidx,
-                                               const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
-                                               uint32_t ebits, uint32_t ewords, uint32_t w,
-                                               uint64_t* __restrict__ out, uint32_t count,
-                                               uint32_t* __restrict__ table, uint32_t tstride, uint32_t tbytes,
-                                               uint32_t coff) {
-  const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
+__device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
+                                            const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
+                                            uint32_t ebits, uint32_t ewords, uint32_t w,
+                                            uint64_t* __restrict__ out, uint32_t count, uint32_t* __restrict__ table,
+                                            uint32_t tstride, uint32_t tbytes, uint32_t coff, uint32_t tile0,
+                                            uint32_t wcol, uint32_t* s_ctx) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t gid = tile0 + lane;
   const bool live = gid < count;
   const uint32_t inst = live ? gid : count - 1;
   uint32_t c = cidx ? cidx[inst] : inst + coff;
@@ -166,18 +173,17 @@ __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __res
   const uint32_t* cn = ctx.n + c;
   const uint32_t* cnp = ctx.np + c;
   const size_t cs = ctx.stride;
-  // table: entry e, limb i of this lane at byte (e * N + i) * tstride * 4 + gid * 4
+  // table: entry e, limb i of this lane at byte (e * N + i) * tstride * 4 + wcol * 4
   const __amdgpu_buffer_rsrc_t tr = make_buf(table, tbytes);
-  const uint32_t tvo = gid * 4u;
+  const uint32_t tvo = wcol * 4u;
   const uint32_t tls = tstride * 4u;  // bytes between consecutive limbs
   const uint64_t* e64 = ex + (size_t)inst * ewords;
 
   const uint32_t nent = 1u << w;
   const uint32_t nwin = ebits ? (ebits + w - 1) / w : 1u;
 
-  __shared__ uint32_t s_ctx[2 * N * 64];
-  stage_ctx<N>(s_ctx, cn, cnp, cs);
-  const uint32_t* sm = s_ctx + threadIdx.x;
+  stage_ctx<N>(s_ctx, cn, cnp, cs, lane);
+  const uint32_t* sm = s_ctx + lane;
 
   // G[0] = R mod N
   for (int i = 0; i < N; ++i) bstore(tr, ctx.r1[(size_t)i * cs + c], tvo, (uint32_t)i * tls);
@@ -275,6 +281,19 @@ __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __res
   sfor<0, N>([&](auto I) { m[decltype(I)::value] = sm[decltype(I)::value * 64]; });
   canon<N>(y, m);
   if (live) contract<N, BW>(y, out + (size_t)inst * BW);
+}
+
+template <int N, int BW, bool TRUNC>
+__global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __restrict__ cidx,
+                                               const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
+                                               uint32_t ebits, uint32_t ewords, uint32_t w,
+                                               uint64_t* __restrict__ out, uint32_t count,
+                                               uint32_t* __restrict__ table, uint32_t tstride, uint32_t tbytes,
+                                               uint32_t coff) {
+  __shared__ uint32_t s_ctx[2 * N * 64];
+  const uint32_t tile0 = blockIdx.x * 64;
+  modexp_tile<N, BW, TRUNC>(ctx, cidx, base, ex, ebits, ewords, w, out, count, table, tstride, tbytes, coff, tile0,
+                            tile0 + (threadIdx.x & 63u), s_ctx);
 }
 
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmontexp.so")
 
 MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EUNSUPPORTED = 0, 1, 2, 3, 4
-MX_REDC_TRUNC, MX_REDC_PLAIN = 0, 1
+MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK = 0, 1, 2
 SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
@@ -31,8 +31,21 @@ _SIGS = {
     "mont_mul_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _U32, _U32, _P]),
     "mont_sqr_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P]),
     "modexp_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P]),
+    "mx_mixed_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), _P, _U32]),
+    "mx_mixed_plan_launch": (ctypes.c_int, [_P, _P]),
+    "mx_mixed_plan_launch_graph": (ctypes.c_int, [_P, _P]),
+    "mx_mixed_plan_query": (ctypes.c_int, [_P, ctypes.POINTER(_U32), ctypes.POINTER(_U32), _P]),
+    "mx_mixed_plan_destroy": (None, [_P]),
+    "mx_tune_modexp": (ctypes.c_int, [_P, _U32, _U32, _P, _U32, _U32, _U32, ctypes.POINTER(_U32),
+                                      ctypes.POINTER(_U32), ctypes.POINTER(ctypes.c_float), _P]),
     "mont_last_error": (ctypes.c_char_p, []),
 }
+
+
+class BatchDesc(ctypes.Structure):
+    """mx_batch_desc of include/montexp.h."""
+    _fields_ = [("ctx", _P), ("ctx_idx", _P), ("base", _P), ("exp", _P), ("out", _P), ("n", _U32),
+                ("exp_bits", _U32), ("window", _U32), ("flags", _U32), ("tile_cost", ctypes.c_float)]
 EXPORTS = tuple(_SIGS)
 
 _lib = None
@@ -172,7 +185,7 @@ def _check_idx(ctx_idx, n, ctx):
         raise ValueError("ctx_idx: expected int32 device tensor [%d]" % n)
 
 
-def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None):
+def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=False):
     """REDC(a*b) per instance; a, b: int64 device tensors [n, mont_words]."""
     n = a.shape[0]
     if out is None:
@@ -181,12 +194,13 @@ def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None):
     for nm, t in (("a", a), ("b", b), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    _check(lib().mont_mul_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(b), _ptr(out), n,
-                                MX_REDC_PLAIN if plain else MX_REDC_TRUNC, _stream_ptr(stream)))
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | (MX_IMPL_BLOCK if block else 0)
+    _check(lib().mont_mul_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(b), _ptr(out), n, flags,
+                                _stream_ptr(stream)))
     return out
 
 
-def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None):
+def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=False):
     """REDC(a^2) per instance; a: int64 device tensor [n, mont_words]."""
     n = a.shape[0]
     if out is None:
@@ -195,12 +209,12 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None):
     for nm, t in (("a", a), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    _check(lib().mont_sqr_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(out), n,
-                                MX_REDC_PLAIN if plain else MX_REDC_TRUNC, _stream_ptr(stream)))
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | (MX_IMPL_BLOCK if block else 0)
+    _check(lib().mont_sqr_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(out), n, flags, _stream_ptr(stream)))
     return out
 
 
-def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None):
+def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None, block=False):
     """base^exp mod N per instance; base: int64 [n, words], exp: int64 [n, ceil(exp_bits/64)]."""
     n = base.shape[0]
     if out is None:
@@ -211,10 +225,68 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
     if exp_bits:
         _check_rows("exp", exp, n, words_for(exp_bits))
     _check_idx(ctx_idx, n, ctx)
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | (MX_IMPL_BLOCK if block else 0)
     _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,
-                              window, _ptr(out), n, MX_REDC_PLAIN if plain else MX_REDC_TRUNC,
-                              _stream_ptr(stream)))
+                              window, _ptr(out), n, flags, _stream_ptr(stream)))
     return out
+
+
+class MixedPlan:
+    """One persistent launch over several size-class batches (mx_mixed_plan_*).
+
+    batches: list of dicts with keys ctx, base, exp, exp_bits, out and
+    optionally window, block (bool), ctx_idx, tile_cost.  The device buffers
+    are captured by the plan; every launch reads and writes them.
+    """
+
+    def __init__(self, batches):
+        descs = (BatchDesc * len(batches))()
+        self._keep = []
+        for k, b in enumerate(batches):
+            ctx, base, exp, out = b["ctx"], b["base"], b["exp"], b["out"]
+            n = base.shape[0]
+            _check_rows("base", base, n, ctx.words)
+            _check_rows("out", out, n, ctx.words)
+            if b["exp_bits"]:
+                _check_rows("exp", exp, n, words_for(b["exp_bits"]))
+            _check_idx(b.get("ctx_idx"), n, ctx)
+            d = descs[k]
+            d.ctx, d.ctx_idx = ctx.handle, _ptr(b.get("ctx_idx"))
+            d.base, d.exp, d.out = _ptr(base), _ptr(exp) if b["exp_bits"] else None, _ptr(out)
+            d.n, d.exp_bits, d.window = n, b["exp_bits"], b.get("window", 0)
+            d.flags = MX_IMPL_BLOCK if b.get("block") else 0
+            d.tile_cost = float(b.get("tile_cost", 0.0))
+            self._keep.append(b)
+        self._h = ctypes.c_void_p()
+        _check(lib().mx_mixed_plan_create(ctypes.byref(self._h), descs, len(batches)))
+        nj, ns = _U32(), _U32()
+        win = (_U32 * len(batches))()
+        _check(lib().mx_mixed_plan_query(self._h, ctypes.byref(nj), ctypes.byref(ns), win))
+        self.njobs, self.nslots, self.windows = nj.value, ns.value, list(win)
+
+    def launch(self, stream=None, graph=False):
+        f = lib().mx_mixed_plan_launch_graph if graph else lib().mx_mixed_plan_launch
+        _check(f(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if self._h:
+            lib().mx_mixed_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune_modexp(ctx, n, exp_bits, windows=(3, 4, 5, 6), try_block=True, reps=2, stream=None):
+    """Fastest (window, flags) for this context's class; returns (window, flags, ms_per_64_tile)."""
+    arr = (_U32 * len(windows))(*windows)
+    bw, bf, bms = _U32(), _U32(), ctypes.c_float()
+    _check(lib().mx_tune_modexp(ctx.handle, n, exp_bits, arr, len(windows), 1 if try_block else 0, reps,
+                                ctypes.byref(bw), ctypes.byref(bf), ctypes.byref(bms), _stream_ptr(stream)))
+    return bw.value, bf.value, bms.value
 
 
 def to_device(words_u64, device="cuda"):

@@ -1,0 +1,138 @@
+"""GPU: block kernels vs register-resident kernels, the mixed-size persistent
+launch (alone == in the mix, graph replays), and the autotuner."""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_18129_amd import workload as wl
+from tests.gpu_util import dev_ints, ints_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_18129_amd import montexp
+    montexp.lib()
+    return montexp
+
+
+@pytest.mark.parametrize("bits", [1024, 2048])
+def test_block_kernels_match_register_kernels(mx, bits):
+    n = 70
+    mods = wl.random_moduli(wl.stream(11, "moduli"), bits, n)
+    ctx = mx.Context(mods, bits)
+    g = wl.stream(11, "ops_a")
+    A = wl.random_below(g, mods, bits, scale=2)
+    B = wl.random_below(g, mods, bits, scale=2)
+    a, b = ints_dev(A, ctx.mont_words), ints_dev(B, ctx.mont_words)
+    for plain in (False, True):
+        assert dev_ints(mx.mont_mul(ctx, a, b, plain=plain, block=True)) == dev_ints(mx.mont_mul(ctx, a, b, plain=plain))
+        assert dev_ints(mx.mont_sqr(ctx, a, plain=plain, block=True)) == dev_ints(mx.mont_sqr(ctx, a, plain=plain))
+    base = wl.random_below_fast(wl.stream(11, "bases"), mods, bits)
+    exps = wl.random_exponents(wl.stream(11, "exps"), bits, n)
+    bd, ed = mx.to_device(base), mx.to_device(exps)
+    r_blk = dev_ints(mx.modexp(ctx, bd, ed, bits, window=4, block=True))
+    assert r_blk == dev_ints(mx.modexp(ctx, bd, ed, bits, window=4))
+    M, Bs, Es = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
+    assert r_blk[0] == oracle.modexp(Bs[0], Es[0], M[0], bits)
+    ctx.close()
+
+
+def test_block_flag_unsupported_class(mx):
+    ctx = mx.Context(wl.random_moduli(wl.stream(12, "moduli"), 256, 1), 256)
+    a = ints_dev([1], ctx.mont_words)
+    with pytest.raises(mx.MontError) as ei:
+        mx.mont_mul(ctx, a, a, block=True)
+    assert ei.value.status == mx.MX_EUNSUPPORTED
+    ctx.close()
+
+
+def _mixed_inputs(mx, counts, k=13):
+    import torch
+    batches, ref = [], []
+    for bits, n in counts.items():
+        mods = wl.random_moduli(wl.stream(k, "moduli"), bits, n)
+        base = wl.random_below_fast(wl.stream(k, "bases"), mods, bits)
+        exps = wl.random_exponents(wl.stream(k, "exps"), bits, n)
+        ctx = mx.Context(mods, bits)
+        b = {"ctx": ctx, "base": mx.to_device(base), "exp": mx.to_device(exps), "exp_bits": bits,
+             "out": torch.zeros((n, ctx.words), dtype=torch.int64, device="cuda")}
+        batches.append(b)
+        ref.append((mods, base, exps))
+    return batches, ref
+
+
+def test_mixed_plan_matches_single_class_and_oracle(mx):
+    import torch
+    counts = {1024: 130, 2048: 70, 3072: 65, 4096: 64}
+    batches, ref = _mixed_inputs(mx, counts)
+    batches[1]["block"] = False
+    plan = mx.MixedPlan(batches)
+    assert plan.njobs == sum((n + 63) // 64 for n in counts.values())
+    plan.launch()
+    torch.cuda.synchronize()
+    for b, (mods, base, exps), bits in zip(batches, ref, counts):
+        got = dev_ints(b["out"])
+        alone = dev_ints(mx.modexp(b["ctx"], b["base"], b["exp"], bits, window=plan.windows[list(counts).index(bits)]))
+        assert got == alone, bits  # the same result alone and in the mix
+        M, B, E = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
+        i = len(M) - 1
+        assert got[i] == oracle.modexp(B[i], E[i], M[i], bits), bits
+    plan.close()
+    for b in batches:
+        b["ctx"].close()
+
+
+def test_mixed_plan_graph_replays(mx):
+    import torch
+    counts = {1024: 100, 2048: 64}
+    batches, ref = _mixed_inputs(mx, counts, k=14)
+    batches[0]["block"] = True
+    plan = mx.MixedPlan(batches)
+    expect = []
+    for b, bits in zip(batches, counts):
+        expect.append(dev_ints(mx.modexp(b["ctx"], b["base"], b["exp"], bits, window=plan.windows[len(expect)],
+                                         block=b.get("block", False))))
+    for rep in range(3):
+        for b in batches:
+            b["out"].zero_()
+        torch.cuda.synchronize()
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        for b, e in zip(batches, expect):
+            assert dev_ints(b["out"]) == e, rep
+    # the graph reads the buffers at replay time: new exponents give new results
+    b0 = batches[0]
+    b0["exp"].copy_(torch.roll(b0["exp"], 1, 0))
+    plan.launch(graph=True)
+    torch.cuda.synchronize()
+    again = dev_ints(mx.modexp(b0["ctx"], b0["base"], b0["exp"], 1024, window=plan.windows[0], block=True))
+    assert dev_ints(b0["out"]) == again
+    plan.close()
+    for b in batches:
+        b["ctx"].close()
+
+
+def test_mixed_plan_rejects_bad_batches(mx):
+    import torch
+    ctx = mx.Context(wl.random_moduli(wl.stream(15, "moduli"), 512, 4), 512)
+    t = torch.zeros((4, ctx.words), dtype=torch.int64, device="cuda")
+    with pytest.raises(mx.MontError) as ei:
+        mx.MixedPlan([{"ctx": ctx, "base": t, "exp": t, "exp_bits": 512, "out": t}])
+    assert ei.value.status == mx.MX_EUNSUPPORTED
+    ctx.close()
+
+
+def test_autotuner_picks_a_candidate(mx, tmp_path):
+    from paper_2410_18129_amd import autotune
+    plans = autotune.plan_for([1024], path=str(tmp_path / "cache.json"), n=512)
+    p = plans[1024]
+    assert p["window"] in autotune.CANDIDATES[1024] and p["ms_per_tile"] > 0
+    again = autotune.plan_for([1024], path=str(tmp_path / "cache.json"), n=512)  # cached, no re-measure
+    assert again == plans
