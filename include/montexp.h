@@ -107,6 +107,18 @@ mx_status modexp_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint6
                        uint32_t exp_bits, uint32_t window, uint64_t *out, uint32_t n, uint32_t flags,
                        void *stream);
 
+/* As modexp_batch, with a caller-owned device workspace of ws_bytes bytes
+ * instead of the context's: no allocation and no lock, so calls on one
+ * context may overlap on different streams as long as each has its own
+ * workspace.  A workspace smaller than modexp_ws_bytes(ctx, n, ...) is used
+ * for n in several launches (MX_EINVAL if it cannot hold 64 instances). */
+mx_status modexp_batch_ws(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint64_t *base, const uint64_t *exp,
+                          uint32_t exp_bits, uint32_t window, uint64_t *out, uint32_t n, uint32_t flags, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Workspace bytes a single launch of n instances needs for this window and flags. */
+mx_status modexp_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t window, uint32_t flags, size_t *bytes);
+
 /* ---- mixed sizes in one persistent launch ----------------------------------
  * For callers that hold batches of several size classes at once (not a
  * construct of the paper, which exponentiates one size per call): the

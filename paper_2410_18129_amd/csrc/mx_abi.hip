@@ -246,10 +246,9 @@ mx_status mont_sqr_batch(const mont_ctx* ctx, const uint32_t* ctx_idx, const uin
   return mont_common("mont_sqr_batch", ctx, ctx_idx, a, a, out, n, flags, stream, true);
 }
 
-mx_status modexp_batch(const mont_ctx* cctx, const uint32_t* ctx_idx, const uint64_t* base, const uint64_t* exp,
-                       uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n, uint32_t flags, void* stream) {
-  static const char* name = "modexp_batch";
-  mont_ctx* ctx = const_cast<mont_ctx*>(cctx);
+static mx_status modexp_common(const char* name, mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* base,
+                               const uint64_t* exp, uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n,
+                               uint32_t flags, void* user_ws, size_t user_ws_bytes, void* stream) {
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!base || !out || (exp_bits && !exp)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
@@ -264,24 +263,65 @@ mx_status modexp_batch(const mont_ctx* cctx, const uint32_t* ctx_idx, const uint
   const uint32_t ewords = (exp_bits + 63) / 64;
   const uint32_t W = words_for(ctx->bits);
   const uint32_t rows = ctx->ops->ws_rows(impl, true, w);
-  const uint32_t chunk = chunk_for(rows, n);
+  uint32_t chunk = chunk_for(rows, n);
   if (chunk == 0) return fail(MX_EUNSUPPORTED, "%s: window %u too large for this size class", name, w);
-  const uint32_t tstride = round_up(chunk, 64);
-  const size_t need = (size_t)rows * tstride * sizeof(uint32_t);
+  void* ws = nullptr;
+  size_t need = 0;
+  uint32_t tstride = 0;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
-  std::lock_guard<std::mutex> lk(ctx->ws_mu);
-  mx_status ms = ensure_ws(ctx, need, name);
-  if (ms != MX_OK) return ms;
+  std::unique_lock<std::mutex> lk(ctx->ws_mu, std::defer_lock);
+  if (user_ws) {
+    // instances per launch limited by the caller's buffer
+    const uint64_t fit = (user_ws_bytes / ((uint64_t)rows * sizeof(uint32_t))) / 64 * 64;
+    if (fit == 0) return fail(MX_EINVAL, "%s: workspace of %zu bytes is smaller than one tile", name, user_ws_bytes);
+    if (fit < chunk) chunk = (uint32_t)fit;
+    tstride = round_up(chunk, 64);
+    need = (size_t)rows * tstride * sizeof(uint32_t);
+    ws = user_ws;
+  } else {
+    tstride = round_up(chunk, 64);
+    need = (size_t)rows * tstride * sizeof(uint32_t);
+    lk.lock();
+    mx_status ms = ensure_ws(ctx, need, name);
+    if (ms != MX_OK) return ms;
+    ws = ctx->ws;
+  }
   const bool trunc = !(flags & MX_REDC_PLAIN);
   for (uint32_t off = 0; off < n; off += chunk) {
     const uint32_t cnt = n - off < chunk ? n - off : chunk;
     hipError_t e = ctx->ops->modexp(impl, trunc, ctx->dev, ctx_idx ? ctx_idx + off : nullptr, base + (size_t)off * W,
                                     exp_bits ? exp + (size_t)off * ewords : exp, exp_bits, ewords, w,
-                                    out + (size_t)off * W, cnt, (uint32_t*)ctx->ws, tstride, (uint32_t)need,
+                                    out + (size_t)off * W, cnt, (uint32_t*)ws, tstride, (uint32_t)need,
                                     ctx_idx ? 0u : off, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(e, name);
   }
+  return MX_OK;
+}
+
+mx_status modexp_batch(const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* base, const uint64_t* exp,
+                       uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n, uint32_t flags, void* stream) {
+  return modexp_common("modexp_batch", const_cast<mont_ctx*>(ctx), ctx_idx, base, exp, exp_bits, window, out, n,
+                       flags, nullptr, 0, stream);
+}
+
+mx_status modexp_batch_ws(const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* base, const uint64_t* exp,
+                          uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n, uint32_t flags, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!ws) return fail(MX_EINVAL, "modexp_batch_ws: workspace is NULL");
+  return modexp_common("modexp_batch_ws", const_cast<mont_ctx*>(ctx), ctx_idx, base, exp, exp_bits, window, out, n,
+                       flags, ws, ws_bytes, stream);
+}
+
+mx_status modexp_ws_bytes(const mont_ctx* ctx, uint32_t n, uint32_t window, uint32_t flags, size_t* bytes) {
+  if (!ctx || !bytes) return fail(MX_EINVAL, "modexp_ws_bytes: NULL argument");
+  const int impl = (flags & MX_IMPL_BLOCK) ? 1 : 0;
+  if (impl && !ctx->ops->has_block) return fail(MX_EUNSUPPORTED, "modexp_ws_bytes: no block kernels");
+  if (window > 8) return fail(MX_EINVAL, "modexp_ws_bytes: window %u outside 1..8", window);
+  const uint32_t w = window ? window : default_window(ctx->bits);
+  const uint32_t rows = ctx->ops->ws_rows(impl, true, w);
+  const uint32_t chunk = chunk_for(rows, n ? n : 1);
+  *bytes = (size_t)rows * round_up(chunk ? chunk : 64, 64) * sizeof(uint32_t);
   return MX_OK;
 }
 

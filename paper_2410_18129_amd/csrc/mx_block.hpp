@@ -115,23 +115,35 @@ __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const Lane
   using Lay = BlkLayout<H, K>;
   constexpr uint32_t n = Lay::n;
   // ---- product T = Y * B (or Y^2), Section 2 at block level --------------
+  // Within a row i the next operand block is loaded while the current block
+  // product runs, and the accumulator rows are read before it: all memory
+  // latency except the first block's overlaps the multiply-accumulates.
   zero_rows(ws, Lay::T, 2 * n + 1);
 #pragma nounroll
   for (uint32_t i = 0; i < K; ++i) {
-    uint32_t a[H];
+    uint32_t a[H], b[H];
     ld_rows<H>(ws, Lay::Y + i * H, a);
+    const uint32_t src = sqr ? Lay::Y : Lay::B;
+    const uint32_t j0 = sqr ? i : 0u;
+    ld_rows<H>(ws, src + j0 * H, b);
 #pragma nounroll
-    for (uint32_t j = sqr ? i : 0u; j < K; ++j) {
+    for (uint32_t j = j0; j < K; ++j) {
+      uint32_t acc[2 * H], bn[H];
+      ld_rows<2 * H>(ws, Lay::T + (i + j) * H, acc);
+      if (j + 1 < K) ld_rows<H>(ws, src + (j + 1) * H, bn);
+      compiler_fence();
       uint32_t t[2 * H];
+      uint32_t mult = 1u;
       if (sqr && j == i) {
         sqr_sb<H>(a, t);
-        add_rows<2 * H>(ws, Lay::T + (i + j) * H, t, 1u);
       } else {
-        uint32_t b[H];
-        ld_rows<H>(ws, (sqr ? Lay::Y : Lay::B) + j * H, b);
         mul_sb<H>(a, b, t);
-        add_rows<2 * H>(ws, Lay::T + (i + j) * H, t, sqr ? 2u : 1u);
+        mult = sqr ? 2u : 1u;
       }
+      sfor<0, 2 * H>([&](auto I) { acc[decltype(I)::value] += t[decltype(I)::value] * mult; });
+      st_rows<2 * H>(ws, Lay::T + (i + j) * H, acc);
+      compiler_fence();
+      if (j + 1 < K) sfor<0, H>([&](auto I) { b[decltype(I)::value] = bn[decltype(I)::value]; });
     }
   }
   norm_rows<H>(ws, Lay::T, 2 * n + 1);
@@ -139,21 +151,32 @@ __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const Lane
   zero_rows(ws, Lay::Q, n);
 #pragma nounroll
   for (uint32_t i = 0; i < K; ++i) {
-    uint32_t a[H];
+    uint32_t a[H], b[H];
     ld_rows<H>(ws, Lay::T + i * H, a);
+    ld_rows<H>(cnp, 0, b);
 #pragma nounroll
     for (uint32_t j = 0; i + j < K; ++j) {
-      uint32_t b[H];
-      ld_rows<H>(cnp, j * H, b);
-      if (i + j + 1 < K) {
+      uint32_t acc[2 * H], bn[H];
+      const bool full = i + j + 1 < K;
+      if (full)
+        ld_rows<2 * H>(ws, Lay::Q + (i + j) * H, acc);
+      else
+        ld_rows<H>(ws, Lay::Q + (i + j) * H, *reinterpret_cast<uint32_t(*)[H]>(acc));
+      if (i + j + 1 < K) ld_rows<H>(cnp, (j + 1) * H, bn);
+      compiler_fence();
+      if (full) {
         uint32_t t[2 * H];
         mul_sb<H>(a, b, t);
-        add_rows<2 * H>(ws, Lay::Q + (i + j) * H, t, 1u);
+        sfor<0, 2 * H>([&](auto I) { acc[decltype(I)::value] += t[decltype(I)::value]; });
+        st_rows<2 * H>(ws, Lay::Q + (i + j) * H, acc);
       } else {
         uint32_t l[H];
         lo_sb<H>(a, b, l);
-        add_rows<H>(ws, Lay::Q + (i + j) * H, l, 1u);
+        sfor<0, H>([&](auto I) { acc[decltype(I)::value] += l[decltype(I)::value]; });
+        st_rows<H>(ws, Lay::Q + (i + j) * H, *reinterpret_cast<uint32_t(*)[H]>(acc));
       }
+      compiler_fence();
+      if (i + j + 1 < K) sfor<0, H>([&](auto I) { b[decltype(I)::value] = bn[decltype(I)::value]; });
     }
   }
   (void)norm_rows<H>(ws, Lay::Q, n);  // the carry out of limb n - 1 is dropped: mod R
@@ -165,25 +188,37 @@ __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const Lane
   copy_rows<H>(ws, Lay::S, ws, Lay::T + c0, slen);
 #pragma nounroll
   for (uint32_t i = 0; i < K; ++i) {
-    uint32_t a[H];
+    uint32_t a[H], b[H];
     ld_rows<H>(ws, Lay::Q + i * H, a);
+    const uint32_t j0 = (TRUNC && i + 2 < K) ? K - 2 - i : 0u;
+    ld_rows<H>(cn, j0 * H, b);
 #pragma nounroll
-    for (uint32_t j = (TRUNC && i + 2 < K) ? K - 2 - i : 0u; j < K; ++j) {
-      uint32_t b[H];
-      ld_rows<H>(cn, j * H, b);
+    for (uint32_t j = j0; j < K; ++j) {
+      uint32_t bn[H];
+      if (j + 1 < K) ld_rows<H>(cn, (j + 1) * H, bn);
       if (!TRUNC || i + j >= K) {
+        uint32_t acc[2 * H];
+        ld_rows<2 * H>(ws, Lay::S + (i + j) * H - c0, acc);
+        compiler_fence();
         uint32_t t[2 * H];
         mul_sb<H>(a, b, t);
-        add_rows<2 * H>(ws, Lay::S + (i + j) * H - c0, t, 1u);
+        sfor<0, 2 * H>([&](auto I) { acc[decltype(I)::value] += t[decltype(I)::value]; });
+        st_rows<2 * H>(ws, Lay::S + (i + j) * H - c0, acc);
       } else if (i + j + 1 == K) {
+        uint32_t acc[H + 2];
+        ld_rows<H + 2>(ws, Lay::S, acc);
+        compiler_fence();
         uint32_t v[H + 2];
         hi_sb<H>(a, b, v);
-        add_rows<H + 2>(ws, Lay::S, v, 1u);
+        sfor<0, H + 2>([&](auto I) { acc[decltype(I)::value] += v[decltype(I)::value]; });
+        st_rows<H + 2>(ws, Lay::S, acc);
       } else {  // i + j == K - 2: its top partial product sits at column n - 2
         const uint64_t p = (uint64_t)a[H - 1] * b[H - 1];
         uint32_t v[2] = {(uint32_t)p & kLimbMask, (uint32_t)(p >> kLimbBits)};
         add_rows<2>(ws, Lay::S, v, 1u);
       }
+      compiler_fence();
+      if (j + 1 < K) sfor<0, H>([&](auto I) { b[decltype(I)::value] = bn[decltype(I)::value]; });
     }
   }
   if constexpr (TRUNC) {

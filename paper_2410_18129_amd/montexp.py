@@ -31,6 +31,8 @@ _SIGS = {
     "mont_mul_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _U32, _U32, _P]),
     "mont_sqr_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P]),
     "modexp_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P]),
+    "modexp_batch_ws": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P, ctypes.c_size_t, _P]),
+    "modexp_ws_bytes": (ctypes.c_int, [_P, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_size_t)]),
     "mx_mixed_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), _P, _U32]),
     "mx_mixed_plan_launch": (ctypes.c_int, [_P, _P]),
     "mx_mixed_plan_launch_graph": (ctypes.c_int, [_P, _P]),
@@ -287,6 +289,39 @@ def tune_modexp(ctx, n, exp_bits, windows=(3, 4, 5, 6), try_block=True, reps=2, 
     _check(lib().mx_tune_modexp(ctx.handle, n, exp_bits, arr, len(windows), 1 if try_block else 0, reps,
                                 ctypes.byref(bw), ctypes.byref(bf), ctypes.byref(bms), _stream_ptr(stream)))
     return bw.value, bf.value, bms.value
+
+
+def modexp_ws_bytes(ctx, n, window=0, block=False):
+    nb = ctypes.c_size_t()
+    _check(lib().modexp_ws_bytes(ctx.handle, n, window, MX_IMPL_BLOCK if block else 0, ctypes.byref(nb)))
+    return nb.value
+
+
+def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, plain=False, stream=None,
+              block=False, n=None):
+    """modexp with a caller-owned workspace tensor (uint8/any dtype, device); n rows of base/exp used."""
+    n = base.shape[0] if n is None else n
+    if out is None:
+        import torch
+        out = torch.empty_like(base)
+    if n > base.shape[0] or n > out.shape[0] or (exp_bits and n > exp.shape[0]):
+        raise ValueError("n exceeds the buffers")
+    for nm, t in (("base", base), ("out", out)):
+        _check_rows(nm, t, t.shape[0], ctx.words)
+    if exp_bits:
+        _check_rows("exp", exp, exp.shape[0], words_for(exp_bits))
+    if ctx_idx is not None:
+        if ctx_idx.dtype.__str__() != "torch.int32" or ctx_idx.shape[0] < n or not ctx_idx.is_cuda:
+            raise ValueError("ctx_idx: expected int32 device tensor with >= n entries")
+    elif n > ctx.count:
+        raise ValueError("n exceeds the context count (pass ctx_idx)")
+    if not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("ws: expected a contiguous device tensor")
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | (MX_IMPL_BLOCK if block else 0)
+    _check(lib().modexp_batch_ws(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None,
+                                 exp_bits, window, _ptr(out), n, flags, _ptr(ws), ws.numel() * ws.element_size(),
+                                 _stream_ptr(stream)))
+    return out
 
 
 def to_device(words_u64, device="cuda"):
