@@ -54,9 +54,12 @@ typedef enum {
 enum {
   MX_REDC_TRUNC = 0, /* truncated reduction, Section 5 Algorithm 6 (default)  */
   MX_REDC_PLAIN = 1, /* full q*N product, Section 4 Algorithm 3 (B_fma)        */
-  MX_IMPL_BLOCK = 2  /* block-level schoolbook over 37-limb blocks for the
+  MX_IMPL_BLOCK = 2, /* block-level schoolbook over 37-limb blocks for the
                         1024/2048 classes (the only kernels above 2048 bits);
                         same results, MX_EUNSUPPORTED where not built        */
+  MX_MUL_KARATSUBA = 4 /* block kernels whose product (A*B or A^2) is one-level
+                          Karatsuba over half-size block numbers (Section 3):
+                          2048 and 4096 bits; same results                   */
 };
 
 /* Montgomery contexts for `count` moduli of size class `bits` (Section 4:
@@ -125,7 +128,8 @@ mx_status modexp_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t window, uint
  * instances of all batches are cut into 64-instance tiles, ordered by
  * decreasing cost and consumed by one persistent grid (one wavefront per
  * SIMD) through a device work counter.  The truncated reduction is used.
- * Supported classes: 1024, 2048 (optionally MX_IMPL_BLOCK), 3072, 4096. */
+ * Supported classes: 1024, 2048 (optionally MX_IMPL_BLOCK or
+ * MX_MUL_KARATSUBA), 3072, 4096 (optionally MX_MUL_KARATSUBA). */
 typedef struct mx_batch_desc {
   const mont_ctx *ctx;      /* contexts of this batch's class                         */
   const uint32_t *ctx_idx;  /* device, n entries, or NULL: instance i uses context i  */
@@ -135,7 +139,7 @@ typedef struct mx_batch_desc {
   uint32_t n;
   uint32_t exp_bits;
   uint32_t window;          /* 1..8, 0 = library choice                               */
-  uint32_t flags;           /* 0 or MX_IMPL_BLOCK                                     */
+  uint32_t flags;           /* 0, MX_IMPL_BLOCK or MX_MUL_KARATSUBA                   */
   float tile_cost;          /* relative cost of one 64-instance tile, 0 = estimate    */
 } mx_batch_desc;
 
@@ -165,7 +169,8 @@ void mx_mixed_plan_destroy(mx_mixed_plan *plan);
 /* ---- autotuning --------------------------------------------------------------
  * Times modexp_batch on n seeded sample instances of ctx (bases below
  * 2^(bits-1), uniform exp_bits-bit exponents) for each candidate window, and
- * for the block kernels too when try_block and the class has them; returns
+ * for the block and Karatsuba kernels too when try_block and the class has
+ * them; returns
  * the fastest window and flags, and its time per 64-instance tile (the best
  * of `reps` runs, in ms).  Allocates its sample buffers. */
 mx_status mx_tune_modexp(const mont_ctx *ctx, uint32_t n, uint32_t exp_bits, const uint32_t *windows,

@@ -47,7 +47,8 @@ def tune_class(bits, n=4096, reps=2, seed_k=9):
                                       reps=reps)
     finally:
         ctx.close()
-    return {"window": w, "block": bool(flags & mx.MX_IMPL_BLOCK), "ms_per_tile": ms, "sample": n}
+    return {"window": w, "block": bool(flags & mx.MX_IMPL_BLOCK), "karatsuba": bool(flags & mx.MX_MUL_KARATSUBA),
+            "ms_per_tile": ms, "sample": n}
 
 
 def plan_for(classes, path=DEFAULT_CACHE, retune=False, n=4096):

@@ -83,6 +83,13 @@ static mx_status ensure_ws(mont_ctx* ctx, size_t need, const char* name) {
   return MX_OK;
 }
 
+// Kernel family for the flags: 0 register-resident, 1 block, 2 block + Karatsuba; -1 if not built.
+static int impl_of(const mont_ctx* ctx, uint32_t flags) {
+  if (flags & MX_MUL_KARATSUBA) return ctx->ops->has_kara ? 2 : -1;
+  if (flags & MX_IMPL_BLOCK) return ctx->ops->has_block ? 1 : -1;
+  return 0;
+}
+
 // Instances per launch so that rows * padded count * 4 bytes fits one descriptor.
 static uint32_t chunk_for(uint32_t rows, uint32_t n) {
   if (rows == 0) return n;
@@ -207,11 +214,10 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!a || !out || (!sqr && !b)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK))
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
-  const int impl = (flags & MX_IMPL_BLOCK) ? 1 : 0;
-  if (impl && !ctx->ops->has_block)
-    return fail(MX_EUNSUPPORTED, "%s: no block kernels for the %u-bit class", name, ctx->bits);
+  const int impl = impl_of(ctx, flags);
+  if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
@@ -252,11 +258,10 @@ static mx_status modexp_common(const char* name, mont_ctx* ctx, const uint32_t* 
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!base || !out || (exp_bits && !exp)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK))
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
-  const int impl = (flags & MX_IMPL_BLOCK) ? 1 : 0;
-  if (impl && !ctx->ops->has_block)
-    return fail(MX_EUNSUPPORTED, "%s: no block kernels for the %u-bit class", name, ctx->bits);
+  const int impl = impl_of(ctx, flags);
+  if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
   if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   const uint32_t w = window ? window : default_window(ctx->bits);
@@ -315,8 +320,8 @@ mx_status modexp_batch_ws(const mont_ctx* ctx, const uint32_t* ctx_idx, const ui
 
 mx_status modexp_ws_bytes(const mont_ctx* ctx, uint32_t n, uint32_t window, uint32_t flags, size_t* bytes) {
   if (!ctx || !bytes) return fail(MX_EINVAL, "modexp_ws_bytes: NULL argument");
-  const int impl = (flags & MX_IMPL_BLOCK) ? 1 : 0;
-  if (impl && !ctx->ops->has_block) return fail(MX_EUNSUPPORTED, "modexp_ws_bytes: no block kernels");
+  const int impl = impl_of(ctx, flags);
+  if (impl < 0) return fail(MX_EUNSUPPORTED, "modexp_ws_bytes: kernel family not built for this class");
   if (window > 8) return fail(MX_EINVAL, "modexp_ws_bytes: window %u outside 1..8", window);
   const uint32_t w = window ? window : default_window(ctx->bits);
   const uint32_t rows = ctx->ops->ws_rows(impl, true, w);

@@ -110,27 +110,27 @@ __device__ __forceinline__ void copy_rows(const LaneBuf& d, uint32_t dst, const 
 
 // One Montgomery product on the workspace: Y <- REDC(Y * B) or REDC(Y^2).
 // n = K H; context blocks come from the limb-major context arrays.
-template <int H, int K, bool TRUNC>
-__device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const LaneBuf& cn, const LaneBuf& cnp) {
-  using Lay = BlkLayout<H, K>;
-  constexpr uint32_t n = Lay::n;
-  // ---- product T = Y * B (or Y^2), Section 2 at block level --------------
-  // Within a row i the next operand block is loaded while the current block
-  // product runs, and the accumulator rows are read before it: all memory
-  // latency except the first block's overlaps the multiply-accumulates.
-  zero_rows(ws, Lay::T, 2 * n + 1);
+// dst rows (dlen, zeroed here) += the product of the M-block numbers at rows
+// a and b (b ignored when sqr), as redundant limbs.  Within a row the next
+// operand block is loaded while the current block product runs, and the
+// accumulator rows are read before it, so memory latency overlaps the
+// multiply-accumulates.
+template <int H>
+__device__ __forceinline__ void blk_product(bool sqr, const LaneBuf& ws, uint32_t ra, uint32_t rb, uint32_t M,
+                                            uint32_t dst, uint32_t dlen) {
+  zero_rows(ws, dst, dlen);
 #pragma nounroll
-  for (uint32_t i = 0; i < K; ++i) {
+  for (uint32_t i = 0; i < M; ++i) {
     uint32_t a[H], b[H];
-    ld_rows<H>(ws, Lay::Y + i * H, a);
-    const uint32_t src = sqr ? Lay::Y : Lay::B;
+    ld_rows<H>(ws, ra + i * H, a);
+    const uint32_t src = sqr ? ra : rb;
     const uint32_t j0 = sqr ? i : 0u;
     ld_rows<H>(ws, src + j0 * H, b);
 #pragma nounroll
-    for (uint32_t j = j0; j < K; ++j) {
+    for (uint32_t j = j0; j < M; ++j) {
       uint32_t acc[2 * H], bn[H];
-      ld_rows<2 * H>(ws, Lay::T + (i + j) * H, acc);
-      if (j + 1 < K) ld_rows<H>(ws, src + (j + 1) * H, bn);
+      ld_rows<2 * H>(ws, dst + (i + j) * H, acc);
+      if (j + 1 < M) ld_rows<H>(ws, src + (j + 1) * H, bn);
       compiler_fence();
       uint32_t t[2 * H];
       uint32_t mult = 1u;
@@ -141,12 +141,134 @@ __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const Lane
         mult = sqr ? 2u : 1u;
       }
       sfor<0, 2 * H>([&](auto I) { acc[decltype(I)::value] += t[decltype(I)::value] * mult; });
-      st_rows<2 * H>(ws, Lay::T + (i + j) * H, acc);
+      st_rows<2 * H>(ws, dst + (i + j) * H, acc);
       compiler_fence();
-      if (j + 1 < K) sfor<0, H>([&](auto I) { b[decltype(I)::value] = bn[decltype(I)::value]; });
+      if (j + 1 < M) sfor<0, H>([&](auto I) { b[decltype(I)::value] = bn[decltype(I)::value]; });
     }
   }
-  norm_rows<H>(ws, Lay::T, 2 * n + 1);
+}
+
+// rows[dst + i] = rows[dst + i] + sign * rows[src + i] as signed 32-bit limbs, C at a time.
+template <int C>
+__device__ __forceinline__ void acc_rows(const LaneBuf& ws, uint32_t dst, uint32_t src, uint32_t len, int sign) {
+  uint32_t i = 0;
+#pragma nounroll
+  for (; i + C <= len; i += C) {
+    uint32_t x[C], y[C];
+    ld_rows<C>(ws, dst + i, x);
+    ld_rows<C>(ws, src + i, y);
+    sfor<0, C>([&](auto I) {
+      constexpr int k = decltype(I)::value;
+      x[k] = (uint32_t)((int32_t)x[k] + sign * (int32_t)y[k]);
+    });
+    st_rows<C>(ws, dst + i, x);
+  }
+#pragma nounroll
+  for (; i < len; ++i) ws.st(dst + i, (uint32_t)((int32_t)ws.ld(dst + i) + sign * (int32_t)ws.ld(src + i)));
+}
+
+// Normalises signed redundant limbs (the total is non-negative) to 28-bit limbs.
+template <int C>
+__device__ __forceinline__ void norm_rows_signed(const LaneBuf& b, uint32_t row, uint32_t len) {
+  int64_t carry = 0;
+  uint32_t i = 0;
+#pragma nounroll
+  for (; i + C <= len; i += C) {
+    uint32_t x[C];
+    ld_rows<C>(b, row + i, x);
+    sfor<0, C>([&](auto I) {
+      constexpr int k = decltype(I)::value;
+      const int64_t v = (int64_t)(int32_t)x[k] + carry;
+      x[k] = (uint32_t)v & kLimbMask;
+      carry = v >> kLimbBits;  // arithmetic shift: floor division
+    });
+    st_rows<C>(b, row + i, x);
+  }
+#pragma nounroll
+  for (; i < len; ++i) {
+    const int64_t v = (int64_t)(int32_t)b.ld(row + i) + carry;
+    b.st(row + i, (uint32_t)v & kLimbMask);
+    carry = v >> kLimbBits;
+  }
+}
+
+// s = x_lo + x_hi over h = M H limbs (rows), returns the carry bit (0 / 1).
+template <int H>
+__device__ __forceinline__ uint32_t half_sum(const LaneBuf& ws, uint32_t x, uint32_t h, uint32_t s) {
+  uint32_t carry = 0;
+#pragma nounroll
+  for (uint32_t i = 0; i < h; i += H) {
+    uint32_t p[H], q[H];
+    ld_rows<H>(ws, x + i, p);
+    ld_rows<H>(ws, x + h + i, q);
+    sfor<0, H>([&](auto I) {
+      constexpr int k = decltype(I)::value;
+      const uint32_t v = p[k] + q[k] + carry;
+      p[k] = v & kLimbMask;
+      carry = v >> kLimbBits;
+    });
+    st_rows<H>(ws, s + i, p);
+  }
+  return carry;
+}
+
+// One-level Karatsuba (Section 3) at block granularity, K even, M = K/2 blocks
+// per half, beta = 2^(28 M H):  D0 = A0 B0, D2 = A1 B1,
+// D1 = (A0 + A1)(B0 + B1) = SA SB + cA SB beta + cB SA beta + cA cB beta^2 with
+// SA = (A0 + A1) mod beta, cA its carry (and likewise SB, cB), and
+// T = D0 + (D1 - D0 - D2) beta + D2 beta^2 in signed redundant limbs.
+// Three half-size products instead of four (squaring: three half squarings).
+// Rows: T gets the product; D (the S region) and SA, SB (the Q region) are scratch.
+template <int H, int K>
+__device__ __forceinline__ void kara_product(bool sqr, const LaneBuf& ws) {
+  using Lay = BlkLayout<H, K>;
+  constexpr uint32_t n = Lay::n, M = K / 2, h = M * H;
+  constexpr uint32_t D = Lay::S, SA = Lay::Q, SB = Lay::Q + h;
+  static_assert(K % 2 == 0, "Karatsuba needs an even block count");
+  zero_rows(ws, Lay::T, 2 * n + 1);
+  const uint32_t rb = sqr ? Lay::Y : Lay::B;
+  // D0 and D2
+  for (uint32_t half = 0; half < 2; ++half) {
+    blk_product<H>(sqr, ws, Lay::Y + half * h, rb + half * h, M, D, 2 * h + 2);
+    norm_rows<H>(ws, D, 2 * h);
+    acc_rows<H>(ws, Lay::T + 2 * half * h, D, 2 * h, 1);
+    acc_rows<H>(ws, Lay::T + h, D, 2 * h, -1);
+  }
+  // D1
+  const uint32_t ca = half_sum<H>(ws, Lay::Y, h, SA);
+  const uint32_t cb = sqr ? ca : half_sum<H>(ws, Lay::B, h, SB);
+  blk_product<H>(sqr, ws, SA, sqr ? SA : SB, M, D, 2 * h + 2);
+  const uint32_t ma = 0u - ca, mb = 0u - cb;  // all-ones when the carry bit is set
+  uint32_t i = 0;
+#pragma nounroll
+  for (; i < h; i += H) {
+    uint32_t d[H], x[H], y[H];
+    ld_rows<H>(ws, D + h + i, d);
+    ld_rows<H>(ws, SA + i, x);
+    ld_rows<H>(ws, (sqr ? SA : SB) + i, y);
+    sfor<0, H>([&](auto I) {
+      constexpr int k = decltype(I)::value;
+      d[k] += (y[k] & ma) + (x[k] & mb);
+    });
+    st_rows<H>(ws, D + h + i, d);
+  }
+  ws.st(D + 2 * h, ws.ld(D + 2 * h) + (ca & cb));
+  norm_rows<H>(ws, D, 2 * h + 2);
+  acc_rows<H>(ws, Lay::T + h, D, 2 * h + 2, 1);
+  norm_rows_signed<H>(ws, Lay::T, 2 * n + 1);
+}
+
+template <int H, int K, bool TRUNC, bool KARA = false>
+__device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const LaneBuf& cn, const LaneBuf& cnp) {
+  using Lay = BlkLayout<H, K>;
+  constexpr uint32_t n = Lay::n;
+  // ---- product T = Y * B (or Y^2): Section 2 at block level, or Section 3 --
+  if constexpr (KARA) {
+    kara_product<H, K>(sqr, ws);
+  } else {
+    blk_product<H>(sqr, ws, Lay::Y, sqr ? Lay::Y : Lay::B, K, Lay::T, 2 * n + 1);
+    norm_rows<H>(ws, Lay::T, 2 * n + 1);
+  }
   // ---- q = T_lo * N' mod R: pairs i + j <= K - 1 (Algorithm 6 step 1) ------
   zero_rows(ws, Lay::Q, n);
 #pragma nounroll
@@ -267,7 +389,7 @@ __device__ __forceinline__ void contract_rows(const LaneBuf& ws, uint32_t row, u
 }
 
 // ---- batched modmul / modsqr, block version ---------------------------------
-template <int H, int K, bool TRUNC, bool SQR>
+template <int H, int K, bool TRUNC, bool SQR, bool KARA = false>
 __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                  const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
                                                  uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
@@ -286,12 +408,12 @@ __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __r
   const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
   expand_rows<H, K>(ws, Lay::Y, a + (size_t)inst * rw, rw);
   if (!SQR) expand_rows<H, K>(ws, Lay::B, b + (size_t)inst * rw, rw);
-  mont_blk<H, K, TRUNC>(SQR, ws, cn, cnp);
+  mont_blk<H, K, TRUNC, KARA>(SQR, ws, cn, cnp);
   if (live) contract_rows<H, K>(ws, Lay::Y, out + (size_t)inst * rw, rw);
 }
 
 // ---- modexp, block version (same schedule as k_modexp) ----------------------
-template <int H, int K, bool TRUNC>
+template <int H, int K, bool TRUNC, bool KARA = false>
 __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
                                                 const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                 uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
@@ -376,7 +498,7 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
 #pragma nounroll
       for (uint32_t i = 0; i < n; ++i) ws.st(Lay::B + i, i == 0 ? 1u : 0u);
     }
-    mont_blk<H, K, TRUNC>(kind == kSqr, ws, cn, cnp);
+    mont_blk<H, K, TRUNC, KARA>(kind == kSqr, ws, cn, cnp);
     if (store_e >= 0) copy_rows<H>(ws, Lay::G + (uint32_t)store_e * n, ws, Lay::Y, n);
   }
   // canonical result: subtract N once if Y >= N (constant time)
@@ -391,15 +513,15 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
   if (live) contract_rows<H, K>(ws, src, out + (size_t)inst * bw, bw);
 }
 
-template <int H, int K, bool TRUNC>
+template <int H, int K, bool TRUNC, bool KARA = false>
 __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                    const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                    uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
                                                    uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
                                                    uint32_t tstride, uint32_t ws_bytes, uint32_t coff) {
   const uint32_t tile0 = blockIdx.x * 64;
-  modexp_tile_blk<H, K, TRUNC>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count, ws_base, tstride, ws_bytes,
-                               coff, tile0, tile0 + (threadIdx.x & 63u));
+  modexp_tile_blk<H, K, TRUNC, KARA>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count, ws_base, tstride,
+                                     ws_bytes, coff, tile0, tile0 + (threadIdx.x & 63u));
 }
 
 }  // namespace mx

@@ -17,6 +17,7 @@ constexpr int kH = 37;                                    // block limbs
 constexpr int kK = (limbs_for(kBits) + kH - 1) / kH;      // blocks
 constexpr int kN = kBlock ? kH * kK : limbs_for(kBits);   // limbs, R = 2^(28 kN)
 constexpr bool kHasBlk = kN % kH == 0;                    // block kernels also built (same R)
+constexpr bool kHasKara = kHasBlk && kK % 2 == 0;         // one-level Karatsuba needs an even block count
 constexpr int kW = words_for(kBits);                      // canonical values (< N)
 constexpr int kRW = words_for(28 * kN);                   // Montgomery-domain values (< 2N < R)
 
@@ -31,7 +32,7 @@ hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
 // per-lane workspace words: block classes keep Y, B, T, Q, S (and the table)
 // in memory; register-resident classes need only the exponentiation table
 uint32_t ws_rows_fn(int impl, bool modexp, uint32_t w) {
-  if (kBlock || (kHasBlk && impl == 1)) return modexp ? BlkLayout<kH, kK>::rows(w) : BlkLayout<kH, kK>::G;
+  if (kBlock || (kHasBlk && impl >= 1)) return modexp ? BlkLayout<kH, kK>::rows(w) : BlkLayout<kH, kK>::G;
   (void)impl;
   return modexp ? (1u << w) * (uint32_t)kN : 0u;
 }
@@ -40,6 +41,20 @@ hipError_t mont_fn(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint
                    const uint64_t* b, uint64_t* out, uint32_t count, uint32_t* ws, uint32_t tstride,
                    uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
   const uint32_t blocks = (count + 63) / 64;
+  if constexpr (kHasKara) {
+    if (impl == 2) {
+#define MX_L(T, S)                                                                                                \
+  hipLaunchKernelGGL((k_mont_blk<kH, kK, T, S, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count, \
+                     ws, tstride, ws_bytes, coff)
+      if (trunc) {
+        if (sqr) MX_L(true, true); else MX_L(true, false);
+      } else {
+        if (sqr) MX_L(false, true); else MX_L(false, false);
+      }
+#undef MX_L
+      return hipGetLastError();
+    }
+  }
   if constexpr (kBlock || kHasBlk) {
     if (kBlock || impl == 1) {
 #define MX_L(T, S)                                                                                              \
@@ -74,6 +89,17 @@ hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* ci
                      uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out, uint32_t count, uint32_t* ws,
                      uint32_t tstride, uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
   const uint32_t blocks = (count + 63) / 64;
+  if constexpr (kHasKara) {
+    if (impl == 2) {
+      if (trunc)
+        hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex,
+                           ebits, ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+      else
+        hipLaunchKernelGGL((k_modexp_blk<kH, kK, false, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex,
+                           ebits, ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+      return hipGetLastError();
+    }
+  }
   if constexpr (kBlock || kHasBlk) {
     if (kBlock || impl == 1) {
       if (trunc)
@@ -96,7 +122,7 @@ hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* ci
   return hipGetLastError();
 }
 
-const ClassOps kOps = {kBits, kN, kHasBlk, ctx_fn, ws_rows_fn, mont_fn, modexp_fn};
+const ClassOps kOps = {kBits, kN, kHasBlk || kBlock, kHasKara, ctx_fn, ws_rows_fn, mont_fn, modexp_fn};
 
 }  // namespace
 

@@ -21,11 +21,13 @@ struct CtxDev {
 // with `tstride` instances per row (ws_bytes = rows * tstride * 4 < 2 GiB);
 // `coff` is added to the instance index to find its context when cidx is NULL.
 // impl: 0 = the class's default kernels, 1 = block-level schoolbook over
-// 37-limb blocks (available when has_block; the default above 2048 bits).
+// 37-limb blocks (available when has_block; the default above 2048 bits),
+// 2 = block kernels with a one-level Karatsuba product (when has_kara).
 struct ClassOps {
   int bits;
   int limbs;
   bool has_block;
+  bool has_kara;
   hipError_t (*ctx_init)(const uint64_t* mods, const CtxDev& ctx, hipStream_t st);
   uint32_t (*ws_rows)(int impl, bool modexp, uint32_t w);
   hipError_t (*mont)(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,

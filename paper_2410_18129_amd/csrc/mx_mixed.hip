@@ -28,7 +28,9 @@
 namespace mx {
 
 // kernel families reachable from the persistent kernel
-enum Family : uint32_t { kF1024 = 0, kF1024B = 1, kF2048 = 2, kF2048B = 3, kF3072B = 4, kF4096B = 5, kNumFam = 6 };
+enum Family : uint32_t {
+  kF1024 = 0, kF1024B = 1, kF2048 = 2, kF2048B = 3, kF3072B = 4, kF4096B = 5, kF2048K = 6, kF4096K = 7, kNumFam = 8
+};
 constexpr int kMaxMixedBatches = 8;
 
 struct MixedBatch {
@@ -87,6 +89,14 @@ __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
         modexp_tile_blk<37, 3, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 48u, mb.out,
                                      mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
         break;
+      case kF2048K:
+        modexp_tile_blk<37, 2, true, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 32u, mb.out,
+                                           mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
+        break;
+      case kF4096K:
+        modexp_tile_blk<37, 4, true, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u, mb.out,
+                                           mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
+        break;
       default:
         modexp_tile_blk<37, 4, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u, mb.out,
                                      mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
@@ -115,12 +125,18 @@ __global__ void k_fill(uint64_t* p, uint32_t rows, uint32_t words, uint32_t topb
 namespace {
 
 bool family_of(const mont_ctx* c, uint32_t flags, uint32_t* fam) {
-  const bool blk = (flags & MX_IMPL_BLOCK) != 0;
+  const bool blk = (flags & MX_IMPL_BLOCK) != 0, kara = (flags & MX_MUL_KARATSUBA) != 0;
   switch (c->bits) {
-    case 1024: *fam = blk ? mx::kF1024B : mx::kF1024; return true;
-    case 2048: *fam = blk ? mx::kF2048B : mx::kF2048; return true;
-    case 3072: *fam = mx::kF3072B; return true;
-    case 4096: *fam = mx::kF4096B; return true;
+    case 1024:
+      if (kara) return false;
+      *fam = blk ? mx::kF1024B : mx::kF1024;
+      return true;
+    case 2048: *fam = kara ? mx::kF2048K : (blk ? mx::kF2048B : mx::kF2048); return true;
+    case 3072:
+      if (kara) return false;
+      *fam = mx::kF3072B;
+      return true;
+    case 4096: *fam = kara ? mx::kF4096K : mx::kF4096B; return true;
     default: return false;
   }
 }
@@ -157,7 +173,7 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     const mx_batch_desc& d = batches[b];
     if (!d.ctx) return mx_fail(MX_EINVAL, "batch %u: ctx is NULL", b);
     if (d.ctx->device != dev) return mx_fail(MX_EINVAL, "batch %u: context lives on another device", b);
-    if (d.flags & ~(uint32_t)MX_IMPL_BLOCK)
+    if (d.flags & ~(uint32_t)(MX_IMPL_BLOCK | MX_MUL_KARATSUBA))
       return mx_fail(MX_EUNSUPPORTED, "batch %u: the mixed launch runs the truncated reduction only", b);
     if (!family_of(d.ctx, d.flags, &fam[b]))
       return mx_fail(MX_EUNSUPPORTED, "batch %u: %u-bit class not in the mixed launch", b, d.ctx->bits);
@@ -188,7 +204,7 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     const mont_ctx* c = d.ctx;
     // default window: 3 up to 2048 bits (table cache-resident), 5 above (6 needs > 2 GiB per slot set)
     const uint32_t w = d.window ? d.window : (c->bits <= 2048 ? 3u : 5u);
-    const int impl = (d.flags & MX_IMPL_BLOCK) || c->bits > 2048 ? 1 : 0;
+    const int impl = (d.flags & MX_MUL_KARATSUBA) ? 2 : ((d.flags & MX_IMPL_BLOCK) || c->bits > 2048 ? 1 : 0);
     const uint32_t rows = c->ops->ws_rows(impl, true, w);
     const size_t bytes = (size_t)rows * p->args.tstride * sizeof(uint32_t);
     if (bytes > mx::kMaxWsBytes) {
@@ -324,10 +340,13 @@ mx_status mx_tune_modexp(const mont_ctx* ctx, uint32_t n, uint32_t exp_bits, con
   }
   mx_status rs = MX_OK;
   float best = 1e30f;
-  for (uint32_t impl = 0; impl <= (try_block && ctx->ops->has_block && ctx->bits <= 2048 ? 1u : 0u) && e == hipSuccess;
-       ++impl) {
+  const uint32_t fam_flags[3] = {0u, (uint32_t)MX_IMPL_BLOCK, (uint32_t)MX_MUL_KARATSUBA};
+  for (uint32_t impl = 0; impl < 3 && e == hipSuccess; ++impl) {
+    if (impl > 0 && !try_block) break;
+    if (impl == 1 && !ctx->ops->has_block) continue;
+    if (impl == 2 && !ctx->ops->has_kara) continue;
     for (uint32_t k = 0; k < nwin && e == hipSuccess; ++k) {
-      const uint32_t flags = impl ? (uint32_t)MX_IMPL_BLOCK : 0u;
+      const uint32_t flags = fam_flags[impl];
       rs = modexp_batch(ctx, nullptr, base, ex, exp_bits, windows[k], out, n, flags, stream);  // warm-up / growth
       if (rs != MX_OK) break;
       float ms = 1e30f;

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmontexp.so")
 
 MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EUNSUPPORTED = 0, 1, 2, 3, 4
-MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK = 0, 1, 2
+MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA = 0, 1, 2, 4
 SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
@@ -168,6 +168,13 @@ class Context:
             pass
 
 
+def _impl_flags(block):
+    """block: False (default kernels), True (block kernels) or "karatsuba"."""
+    if block == "karatsuba":
+        return MX_MUL_KARATSUBA
+    return MX_IMPL_BLOCK if block else 0
+
+
 def _check_rows(name, t, n, words):
     """Shape/dtype/device checks that keep every kernel access inside the buffers."""
     import torch
@@ -196,7 +203,7 @@ def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=
     for nm, t in (("a", a), ("b", b), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | (MX_IMPL_BLOCK if block else 0)
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block)
     _check(lib().mont_mul_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(b), _ptr(out), n, flags,
                                 _stream_ptr(stream)))
     return out
@@ -211,7 +218,7 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=Fal
     for nm, t in (("a", a), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | (MX_IMPL_BLOCK if block else 0)
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block)
     _check(lib().mont_sqr_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(out), n, flags, _stream_ptr(stream)))
     return out
 
@@ -227,7 +234,7 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
     if exp_bits:
         _check_rows("exp", exp, n, words_for(exp_bits))
     _check_idx(ctx_idx, n, ctx)
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | (MX_IMPL_BLOCK if block else 0)
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block)
     _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,
                               window, _ptr(out), n, flags, _stream_ptr(stream)))
     return out
@@ -256,7 +263,7 @@ class MixedPlan:
             d.ctx, d.ctx_idx = ctx.handle, _ptr(b.get("ctx_idx"))
             d.base, d.exp, d.out = _ptr(base), _ptr(exp) if b["exp_bits"] else None, _ptr(out)
             d.n, d.exp_bits, d.window = n, b["exp_bits"], b.get("window", 0)
-            d.flags = MX_IMPL_BLOCK if b.get("block") else 0
+            d.flags = (MX_MUL_KARATSUBA if b.get("karatsuba") else 0) | (MX_IMPL_BLOCK if b.get("block") else 0)
             d.tile_cost = float(b.get("tile_cost", 0.0))
             self._keep.append(b)
         self._h = ctypes.c_void_p()
@@ -293,7 +300,7 @@ def tune_modexp(ctx, n, exp_bits, windows=(3, 4, 5, 6), try_block=True, reps=2, 
 
 def modexp_ws_bytes(ctx, n, window=0, block=False):
     nb = ctypes.c_size_t()
-    _check(lib().modexp_ws_bytes(ctx.handle, n, window, MX_IMPL_BLOCK if block else 0, ctypes.byref(nb)))
+    _check(lib().modexp_ws_bytes(ctx.handle, n, window, _impl_flags(block), ctypes.byref(nb)))
     return nb.value
 
 
@@ -317,7 +324,7 @@ def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, pl
         raise ValueError("n exceeds the context count (pass ctx_idx)")
     if not ws.is_cuda or not ws.is_contiguous():
         raise ValueError("ws: expected a contiguous device tensor")
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | (MX_IMPL_BLOCK if block else 0)
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block)
     _check(lib().modexp_batch_ws(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None,
                                  exp_bits, window, _ptr(out), n, flags, _ptr(ws), ws.numel() * ws.element_size(),
                                  _stream_ptr(stream)))

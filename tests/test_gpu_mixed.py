@@ -136,3 +136,45 @@ def test_autotuner_picks_a_candidate(mx, tmp_path):
     assert p["window"] in autotune.CANDIDATES[1024] and p["ms_per_tile"] > 0
     again = autotune.plan_for([1024], path=str(tmp_path / "cache.json"), n=512)  # cached, no re-measure
     assert again == plans
+
+
+@pytest.mark.parametrize("bits", [2048, 4096])
+def test_karatsuba_matches_schoolbook(mx, bits):
+    from tests.gpu_util import adversarial_pairs
+    n = 66
+    mods = wl.random_moduli(wl.stream(16, "moduli"), bits, n)
+    M = wl.words_to_ints(mods)
+    g = wl.stream(16, "ops_a")
+    A = wl.random_below(g, mods, bits, scale=2)
+    B = wl.random_below(g, mods, bits, scale=2)
+    # adversarial operands on the first contexts: all-ones halves drive the half-sum carries
+    for k, (x, y) in enumerate(adversarial_pairs(M[0], bits)[:10]):
+        A[k], B[k] = x % (2 * M[k]), y % (2 * M[k])
+    ctx = mx.Context(mods, bits)
+    a, b = ints_dev(A, ctx.mont_words), ints_dev(B, ctx.mont_words)
+    for plain in (False, True):
+        kmul = dev_ints(mx.mont_mul(ctx, a, b, plain=plain, block="karatsuba"))
+        ksqr = dev_ints(mx.mont_sqr(ctx, a, plain=plain, block="karatsuba"))
+        assert kmul == dev_ints(mx.mont_mul(ctx, a, b, plain=plain, block=True))
+        assert ksqr == dev_ints(mx.mont_sqr(ctx, a, plain=plain, block=True))
+    for i in (0, 5, n - 1):
+        assert kmul[i] == oracle.montmul(A[i], B[i], M[i], ctx.r_bits)
+        assert ksqr[i] == oracle.montmul(A[i], A[i], M[i], ctx.r_bits)
+    base = wl.random_below_fast(wl.stream(16, "bases"), mods, bits)
+    exps = wl.random_exponents(wl.stream(16, "exps"), bits, n)
+    bd, ed = mx.to_device(base), mx.to_device(exps)
+    rk = dev_ints(mx.modexp(ctx, bd, ed, bits, window=4, block="karatsuba"))
+    assert rk == dev_ints(mx.modexp(ctx, bd, ed, bits, window=4, block=True))
+    Bs, Es = wl.words_to_ints(base), wl.words_to_ints(exps)
+    assert rk[1] == pow(Bs[1], Es[1], M[1])
+    ctx.close()
+
+
+@pytest.mark.parametrize("bits", [1024, 3072])
+def test_karatsuba_needs_even_block_count(mx, bits):
+    ctx = mx.Context(wl.random_moduli(wl.stream(17, "moduli"), bits, 1), bits)
+    a = ints_dev([1], ctx.mont_words)
+    with pytest.raises(mx.MontError) as ei:
+        mx.mont_mul(ctx, a, a, block="karatsuba")
+    assert ei.value.status == mx.MX_EUNSUPPORTED
+    ctx.close()
