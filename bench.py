@@ -1,16 +1,20 @@
-"""Benchmark: 2048-bit batched constant-time modexp on one MI355X.
+"""Benchmark of the batched truncated-Montgomery exponentiation on one MI355X.
 
 One step = one launch of the whole hot path (context-resident moduli,
-conversion to Montgomery form, window table, 410 windows of 5 squarings + a
-masked table scan + a multiplication, conversion back, canonical output)
-over a batch of 65536 synthetic instances with inputs resident in HBM.
+conversion into Montgomery form, window table, every window's squarings +
+constant-time table scan + multiplication, conversion back, canonical
+output) over 65536 seeded 2048-bit instances, window 5, inputs resident in
+HBM.  The JSON line also carries the other workloads (8 x 1024-bit; 16384 x
+4096-bit schoolbook vs Karatsuba; the 200k mixed-size persistent launch; the
+serving loop's p50/p99) and the oracle timed on the host cores.
 
-Prints one JSON line (see the design doc for every field).  Usage:
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu] [--serve-full]
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -18,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "2048-bit modexp/s (truncated vs plain Montgomery), % int-mul peak; p99 latency"
+KERNEL_SOURCES = ("mx_core.hpp", "mx_kernels.hpp", "mx_class.hip")
 
 
 def parse():
@@ -28,32 +33,65 @@ def parse():
     ap.add_argument("--bits", type=int, default=2048)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--window", type=int, default=5)
+    ap.add_argument("--quick", action="store_true", help="headline only (no other workloads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain-reduction comparison")
+    ap.add_argument("--serve-full", action="store_true", help="serving sweep 50k..400k req/s, 200k requests each")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle instances (0 = 2 per core)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB device-to-device three times (calibrates FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    n = 256 << 20
+    a = torch.ones(n // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "copies": 3}))
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2410_18129_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_id):
+    """HBM bytes per launch from the committed counter summary, if it was taken on these sources."""
+    path = os.path.join(ROOT, "profiles", "modexp2048_w5_traffic.md")
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"source hash: `([0-9a-f]+)`", txt)
+    t = re.search(r"HBM bytes per launch \(scaled\): `([0-9.eE+]+)`", txt)
+    if not m or not t or m.group(1) != kernel_id:
+        return None
+    return float(t.group(1))
 
 
 def cpu_baseline(bits, sample, cores):
     """The oracle (plain C schoolbook + bit-serial reduction + square-and-multiply)
     on a bounded sample of the same workload, one process per core."""
     import multiprocessing as mp
-    import numpy as np
     from paper_2410_18129_amd import workload as wl
-    g = wl.stream(2, "moduli")
-    mods = wl.random_moduli(g, bits, sample)
+    mods = wl.random_moduli(wl.stream(2, "moduli"), bits, sample)
     base = wl.random_below_fast(wl.stream(2, "bases"), mods, bits)
     exps = wl.random_exponents(wl.stream(2, "exps"), bits, sample)
     M, B, E = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
     chunks = [(B[i::cores], E[i::cores], M[i::cores], bits) for i in range(cores)]
-    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
+    with mp.get_context("fork").Pool(cores) as pool:
         pool.map(_oracle_chunk, chunks)
     dt = time.perf_counter() - t0
     return {"value": sample / dt, "unit": "modexp/s", "cores": cores, "kind": "oracle",
-            "sample": "%d x %d-bit modexp (2048-bit exponents), %d worker processes, %.1f s wall" %
-                      (sample, bits, cores, dt)}
+            "sample": "%d x %d-bit modexp (%d-bit exponents), %d worker processes, %.1f s wall" %
+                      (sample, bits, bits, cores, dt)}
 
 
 def _oracle_chunk(args):
@@ -64,95 +102,193 @@ def _oracle_chunk(args):
     return len(b)
 
 
+class Batch:
+    """Seeded inputs for one size class, resident on the device."""
+
+    def __init__(self, mx, bits, n, k, dev):
+        from paper_2410_18129_amd import workload as wl
+        import torch
+        self.bits, self.n = bits, n
+        mods = wl.random_moduli(wl.stream(k, "moduli"), bits, n)
+        self.ctx = mx.Context(mods, bits)
+        self.base = mx.to_device(wl.random_below_fast(wl.stream(k, "bases"), mods, bits), dev)
+        self.exp = mx.to_device(wl.random_exponents(wl.stream(k, "exps"), bits, n), dev)
+        self.out = torch.empty_like(self.base)
+
+
+def time_launches(fn, steps, warmup, stream):
+    """Wall time of `steps` launches after `warmup`, and each launch's kernel time (events on the stream)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [e0.elapsed_time(e1) for e0, e1 in evs]
+
+
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe()
+        return
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); every instance is "
-              "independent, see DESIGN.md for how the batch would shard" % a.gpus, file=sys.stderr)
+        print("bench.py: this build runs on one GPU only (--gpus %d requested); instances are independent, "
+              "DESIGN.md section 9 describes how the batch would shard" % a.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
-    from paper_2410_18129_amd import counts, montexp as mx, workload as wl
-
+    from paper_2410_18129_amd import counts, montexp as mx
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     mx.lib()
     dev = torch.device("cuda:0")
-    bits, n, w = a.bits, a.batch, a.window
-    g = wl.stream(2, "moduli")
-    mods = wl.random_moduli(g, bits, n)
-    base = wl.random_below_fast(wl.stream(2, "bases"), mods, bits)
-    exps = wl.random_exponents(wl.stream(2, "exps"), bits, n)
-    ctx = mx.Context(mods, bits)
-    bd = mx.to_device(base, dev)
-    ed = mx.to_device(exps, dev)
-    out = torch.empty_like(bd)
     stream = torch.cuda.current_stream()
+    bits, n, w = a.bits, a.batch, a.window
 
-    def run(plain, steps, warmup):
-        for _ in range(warmup):
-            mx.modexp(ctx, bd, ed, bits, window=w, out=out, plain=plain, stream=stream)
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        t0 = time.perf_counter()
-        for e0, e1 in evs:
-            e0.record(stream)
-            mx.modexp(ctx, bd, ed, bits, window=w, out=out, plain=plain, stream=stream)
-            e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        kms = [e0.elapsed_time(e1) for e0, e1 in evs]
-        return wall, kms
+    # ---- headline: config 2, 65536 x 2048-bit, window 5, truncated ---------
+    b2 = Batch(mx, bits, n, 2, dev)
 
-    wall, kms = run(False, a.steps, a.warmup)
-    ms_step = wall * 1e3 / a.steps
+    def step(plain=False, win=w):
+        mx.modexp(b2.ctx, b2.base, b2.exp, bits, window=win, out=b2.out, plain=plain, stream=stream)
+
+    wall, kms = time_launches(step, a.steps, a.warmup, stream)
     value = n * a.steps / wall
-    prod = counts.modexp_products(bits, bits, w, trunc=True)
     kavg = sum(kms) / len(kms)
+    prod = counts.modexp_products(bits, bits, w, trunc=True)
     achieved = prod * n / (kavg * 1e-3)
+    khash = kernel_hash()
+    traffic = measured_traffic(khash)
     res = {
         "metric": METRIC, "value": value, "unit": "modexp/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": wall * 1e3 / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": "%d-bit constant-time fixed-window modexp, batch %d, window %d, truncated "
-                               "Montgomery reduction, %d-bit exponents" % (bits, n, w, bits),
+                               "Montgomery reduction, %d-bit exponents (seeded random odd moduli, bases < N)"
+                               % (bits, n, w, bits),
                    "global_batch": n, "bits": bits, "window": w, "limb_bits": 28, "limbs": counts.limbs(bits),
-                   "parallelism": "one instance per lane, single GPU"},
+                   "parallelism": "one instance per lane, one GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": counts.PEAK_MAD_PER_S / 1e12,
-                     "unit": "Tmad/s", "frac": achieved / counts.PEAK_MAD_PER_S, "traffic": None,
-                     "kernel": "k_modexp<74,32,true>", "kernel_ms": kavg,
-                     "work_per_launch": "%d x %d 28x28-bit products" % (n, prod)},
+                     "unit": "Tmad/s", "frac": achieved / counts.PEAK_MAD_PER_S, "traffic": traffic,
+                     "kernel": "k_modexp<74,32,true>", "kernel_ms": kavg, "source_hash": khash,
+                     "work_per_launch": "%d instances x %d 28x28-bit products" % (n, prod)},
     }
-    if not a.no_plain:
-        wall_p, kms_p = run(True, max(2, a.steps // 2), 1)
-        vp = n * len(kms_p) / wall_p
-        prod_p = counts.modexp_products(bits, bits, w, trunc=False)
-        kp = sum(kms_p) / len(kms_p)
-        res["plain"] = {"value": vp, "unit": "modexp/s", "kernel_ms": kp,
-                        "frac": prod_p * n / (kp * 1e-3) / counts.PEAK_MAD_PER_S}
-        res["trunc_speedup"] = value / vp
-    # modmul/s on the same moduli (streaming REDC(a*b), values in [0, 2N))
-    A = mx.to_device(wl.random_below_fast(wl.stream(2, "ops_a"), mods, bits), dev)
-    A = torch.nn.functional.pad(A, (0, ctx.mont_words - ctx.words))
+    wall_p, kms_p = time_launches(lambda: step(plain=True), max(2, a.steps // 2), 1, stream)
+    vp = n * len(kms_p) / wall_p
+    prod_p = counts.modexp_products(bits, bits, w, trunc=False)
+    kp = sum(kms_p) / len(kms_p)
+    res["plain"] = {"value": vp, "unit": "modexp/s", "kernel_ms": kp,
+                    "frac": prod_p * n / (kp * 1e-3) / counts.PEAK_MAD_PER_S}
+    res["trunc_speedup"] = value / vp
+    # the window the library picks for this class (3: the table stays in the last-level cache)
+    tuned = {}
+    for plain in (False, True):
+        wl3, k3 = time_launches(lambda: step(plain=plain, win=3), max(2, a.steps // 2), 1, stream)
+        tuned["plain" if plain else "trunc"] = n * len(k3) / wl3
+        if not plain:
+            p3 = counts.modexp_products(bits, bits, 3, trunc=True)
+            tuned["frac"] = p3 * n / (sum(k3) / len(k3) * 1e-3) / counts.PEAK_MAD_PER_S
+    tuned["trunc_speedup"] = tuned["trunc"] / tuned["plain"]
+    res["window3"] = tuned
+    # modmul / modsqr per second on the same moduli (values in [0, 2N))
+    A = torch.nn.functional.pad(b2.base, (0, b2.ctx.mont_words - b2.ctx.words))
     B = torch.roll(A, 1, 0).contiguous()
     O = torch.empty_like(A)
-    for _ in range(3):
-        mx.mont_mul(ctx, A, B, out=O, stream=stream)
-    torch.cuda.synchronize()
-    reps = 20
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        mx.mont_mul(ctx, A, B, out=O, stream=stream)
-    torch.cuda.synchronize()
-    res["modmul_per_s"] = n * reps / (time.perf_counter() - t0)
+    for name, fn in (("modmul_per_s", lambda: mx.mont_mul(b2.ctx, A, B, out=O, stream=stream)),
+                     ("modsqr_per_s", lambda: mx.mont_sqr(b2.ctx, A, out=O, stream=stream))):
+        wl_, _ = time_launches(fn, 20, 3, stream)
+        res[name] = n * 20 / wl_
+    b2.ctx.close()
+    del b2
+
+    if not a.quick:
+        res["workloads"] = other_workloads(a, mx, counts, dev, stream)
     if not a.no_cpu:
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         cores = max(1, min(cores, 16))
-        sample = a.cpu_sample or 2 * cores
-        res["cpu_baseline"] = cpu_baseline(bits, sample, cores)
-    ctx.close()
+        res["cpu_baseline"] = cpu_baseline(bits, a.cpu_sample or 2 * cores, cores)
     print(json.dumps(res), flush=True)
+
+
+def other_workloads(a, mx, counts, dev, stream):
+    import torch
+    from paper_2410_18129_amd import serving
+    out = {}
+    # ---- config 1: 8 x 1024-bit ------------------------------------------------
+    b1 = Batch(mx, 1024, 8, 1, dev)
+    c1 = {}
+    for plain in (False, True):
+        tag = "plain" if plain else "trunc"
+        wl_, k = time_launches(lambda: mx.modexp(b1.ctx, b1.base, b1.exp, 1024, window=5, out=b1.out, plain=plain,
+                                                 stream=stream), 5, 2, stream)
+        c1["modexp_ms_" + tag] = min(k)
+    out["c1_1024x8"] = c1
+    b1.ctx.close()
+    # ---- config 3: 16384 x 4096-bit, schoolbook vs one-level Karatsuba -------------
+    b3 = Batch(mx, 4096, 16384, 3, dev)
+    c3 = {}
+    for impl in (True, "karatsuba"):
+        tag = "karatsuba" if impl == "karatsuba" else "schoolbook"
+        wl_, k = time_launches(lambda: mx.modexp(b3.ctx, b3.base, b3.exp, 4096, window=6, out=b3.out, block=impl,
+                                                 stream=stream), 2, 1, stream)
+        c3["modexp_per_s_" + tag] = b3.n * 2 / wl_
+        c3["frac_" + tag] = (counts.modexp_products(4096, 4096, 6) * b3.n / (sum(k) / len(k) * 1e-3) /
+                             counts.PEAK_MAD_PER_S)
+        A = torch.nn.functional.pad(b3.base, (0, b3.ctx.mont_words - b3.ctx.words))
+        O = torch.empty_like(A)
+        wl_, _ = time_launches(lambda: mx.mont_mul(b3.ctx, A, A, out=O, block=impl, stream=stream), 5, 1, stream)
+        c3["modmul_per_s_" + tag] = b3.n * 5 / wl_
+    out["c3_4096x16384"] = c3
+    b3.ctx.close()
+    del b3
+    # ---- config 4: 200k mixed sizes, one persistent launch ------------------------------
+    from paper_2410_18129_amd import workload as wl
+    sizes = wl.size_mix(wl.stream(4, "sizes"), 200000)
+    batches, nb = [], {}
+    for c in (1024, 2048, 3072, 4096):
+        nb[c] = int((sizes == c).sum())
+        bb = Batch(mx, c, nb[c], 4 + c, dev)
+        batches.append(bb)
+    plan = mx.MixedPlan([{"ctx": bb.ctx, "base": bb.base, "exp": bb.exp, "exp_bits": bb.bits, "out": bb.out,
+                          "window": 3 if bb.bits <= 2048 else 5} for bb in batches])
+    wl_, k = time_launches(lambda: plan.launch(stream=stream, graph=True), 2, 1, stream)
+    work = sum(counts.modexp_products(bb.bits, bb.bits, 3 if bb.bits <= 2048 else 5) * bb.n for bb in batches)
+    out["c4_mixed_200k"] = {"modexp_per_s": 200000 * 2 / wl_, "ms_per_launch": wl_ * 1e3 / 2,
+                            "counts": nb, "windows": plan.windows, "jobs": plan.njobs, "persistent_waves": plan.nslots,
+                            "frac": work / (sum(k) / len(k) * 1e-3) / counts.PEAK_MAD_PER_S, "hip_graph": True}
+    offline = 200000 * 2 / wl_
+    plan.close()
+    for bb in batches:
+        bb.ctx.close()
+    del batches
+    torch.cuda.synchronize()
+    # ---- config 5: serving, Poisson arrivals over 2000 resident moduli ---------------------
+    rates = (50e3, 100e3, 200e3, 300e3, 400e3) if a.serve_full else (50e3, 100e3, 200e3, 400e3)
+    nreq = 200000 if a.serve_full else 60000
+    # one slot (stream, hence hardware queue) per class: a class's next batch is every request that
+    # arrived while its previous batch ran; the classes' batches overlap on the device
+    maxb = {1024: 65536, 2048: 65536, 3072: 32768, 4096: 32768}
+    sweep = []
+    for r in rates:
+        tr = serving.Trace(nreq, r, k=5)
+        ex = serving.GpuExecutor(tr, maxb, mem_budget=8 << 30, windows={1024: 3, 2048: 3, 3072: 5, 4096: 5},
+                                 max_slots=1)
+        st = serving.Server(ex, tr.classes, maxb).run(tr, timeout_s=300)
+        s = st.stats()
+        s["vs_offline"] = s["throughput"] / offline
+        sweep.append(s)
+        ex.close()
+        del ex, tr
+        torch.cuda.synchronize()
+    out["c5_serving"] = {"requests_per_rate": nreq, "moduli": 2000, "sweep": sweep,
+                         "offline_mixed_modexp_per_s": offline}
+    return out
 
 
 if __name__ == "__main__":

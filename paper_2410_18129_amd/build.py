@@ -43,10 +43,13 @@ def build(jobs=None, only=None, verbose=True):
         units.append(("class_%d" % b, [HIPCC] + FLAGS + ["-DMX_CLASS_BITS=%d" % b, "-c",
                                                        os.path.join(CSRC, "mx_class.hip"),
                                                        "-o", os.path.join(BUILD, "mx_class_%d.o" % b)]))
+    # the issue-rate probe: a standalone program that measures the ALU roofline's issue rates
+    units.append(("issue_rate", [HIPCC] + FLAGS + ["-o", os.path.join(HERE, "issue_rate"),
+                                                  os.path.join(CSRC, "issue_rate.hip")]))
     jobs = jobs or min(len(units), max(1, os.cpu_count() or 1))
     t0 = time.time()
     # largest classes first so they overlap with the small ones
-    units.sort(key=lambda u: -int(u[0].split("_")[1]) if u[0].startswith("class") else
+    units.sort(key=lambda u: -int(u[0].split("_")[1]) if u[0].startswith("class_") else
                (-4096 if u[0] == "mx_mixed" else 0))
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = {ex.submit(_run, cmd): name for name, cmd in units}
