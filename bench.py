@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "2048-bit modexp/s (truncated vs plain Montgomery), % int-mul peak; p99 latency"
 KERNEL_SOURCES = ("mx_core.hpp", "mx_kernels.hpp", "mx_class.hip")
+SERVE_SLOTS = 2  # serving: execution slots per size class
 
 
 def parse():
@@ -142,6 +143,10 @@ def main():
         print("bench.py: this build runs on one GPU only (--gpus %d requested); instances are independent, "
               "DESIGN.md section 9 describes how the batch would shard" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if not a.quick:
+        # the serving workload runs 4 x SERVE_SLOTS streams concurrently: give each its own hardware
+        # queue (HIP reads this once, at its first device call; 4 by default)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(4 * SERVE_SLOTS + 1)
     import torch
     from paper_2410_18129_amd import counts, montexp as mx
     if not torch.cuda.is_available():
@@ -270,15 +275,18 @@ def other_workloads(a, mx, counts, dev, stream):
     torch.cuda.synchronize()
     # ---- config 5: serving, Poisson arrivals over 2000 resident moduli ---------------------
     rates = (50e3, 100e3, 200e3, 300e3, 400e3) if a.serve_full else (50e3, 100e3, 200e3, 400e3)
-    nreq = 200000 if a.serve_full else 60000
-    # one slot (stream, hence hardware queue) per class: a class's next batch is every request that
-    # arrived while its previous batch ran; the classes' batches overlap on the device
+    # a trace spans several batch durations of the slowest class (one 4096-bit exponentiation per
+    # lane takes over a second), so that throughput is not just the fill and drain of a burst
+    span_s, nmin = (5.0, 200000) if a.serve_full else (3.0, 100000)
+    # SERVE_SLOTS execution slots (a stream and a workspace each) per class, each stream on its own
+    # hardware queue; batches of a class are paced about a batch duration / SERVE_SLOTS apart
     maxb = {1024: 65536, 2048: 65536, 3072: 32768, 4096: 32768}
     sweep = []
     for r in rates:
+        nreq = int(max(nmin, r * span_s))
         tr = serving.Trace(nreq, r, k=5)
         ex = serving.GpuExecutor(tr, maxb, mem_budget=8 << 30, windows={1024: 3, 2048: 3, 3072: 5, 4096: 5},
-                                 max_slots=1)
+                                 max_slots=SERVE_SLOTS)
         st = serving.Server(ex, tr.classes, maxb).run(tr, timeout_s=300)
         s = st.stats()
         s["vs_offline"] = s["throughput"] / offline
@@ -286,7 +294,8 @@ def other_workloads(a, mx, counts, dev, stream):
         ex.close()
         del ex, tr
         torch.cuda.synchronize()
-    out["c5_serving"] = {"requests_per_rate": nreq, "moduli": 2000, "sweep": sweep,
+    out["c5_serving"] = {"moduli": 2000, "slots_per_class": SERVE_SLOTS,
+                         "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")), "sweep": sweep,
                          "offline_mixed_modexp_per_s": offline}
     return out
 

@@ -393,16 +393,18 @@ template <int H, int K, bool TRUNC, bool SQR, bool KARA = false>
 __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                  const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
                                                  uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
-                                                 uint32_t tstride, uint32_t ws_bytes, uint32_t coff) {
+                                                 uint32_t ws_bytes, uint32_t coff) {
   using Lay = BlkLayout<H, K>;
   constexpr uint32_t n = Lay::n;
   const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
+  constexpr uint32_t tbytes = Lay::G * 256u;  // this block's region: G rows x 64 lanes
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
   const bool live = gid < count;
   const uint32_t inst = live ? gid : count - 1;
   uint32_t c = cidx ? cidx[inst] : inst + coff;
   c = c < ctx.count ? c : 0u;
   const uint32_t rw = (kLimbBits * n + 63) / 64;
-  const LaneBuf ws{make_buf(ws_base, ws_bytes), gid * 4u, tstride * 4u};
+  const LaneBuf ws{make_buf(ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes), (threadIdx.x & 63u) * 4u, 256u};
   const uint32_t cbytes = n * ctx.stride * 4u;
   const LaneBuf cn{make_buf(ctx.n, cbytes), c * 4u, ctx.stride * 4u};
   const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
@@ -413,13 +415,14 @@ __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __r
 }
 
 // ---- modexp, block version (same schedule as k_modexp) ----------------------
+// tws: this wavefront's own workspace region (BlkLayout rows(w) rows of 64
+// lanes, 256 bytes per row), contiguous in memory.
 template <int H, int K, bool TRUNC, bool KARA = false>
 __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
                                                 const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                 uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
-                                                uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
-                                                uint32_t tstride, uint32_t ws_bytes, uint32_t coff, uint32_t tile0,
-                                                uint32_t wcol) {
+                                                uint64_t* __restrict__ out, uint32_t count, uint32_t* tws,
+                                                uint32_t tws_bytes, uint32_t coff, uint32_t tile0) {
   using Lay = BlkLayout<H, K>;
   constexpr uint32_t n = Lay::n;
   const uint32_t gid = tile0 + (threadIdx.x & 63u);
@@ -427,7 +430,7 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
   const uint32_t inst = live ? gid : count - 1;
   uint32_t c = cidx ? cidx[inst] : inst + coff;
   c = c < ctx.count ? c : 0u;
-  const LaneBuf ws{make_buf(ws_base, ws_bytes), wcol * 4u, tstride * 4u};
+  const LaneBuf ws{make_buf(tws, tws_bytes), (threadIdx.x & 63u) * 4u, 256u};
   const uint32_t cbytes = n * ctx.stride * 4u;
   const LaneBuf cn{make_buf(ctx.n, cbytes), c * 4u, ctx.stride * 4u};
   const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
@@ -518,10 +521,12 @@ __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* _
                                                    const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                    uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
                                                    uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
-                                                   uint32_t tstride, uint32_t ws_bytes, uint32_t coff) {
+                                                   uint32_t ws_bytes, uint32_t coff) {
   const uint32_t tile0 = blockIdx.x * 64;
-  modexp_tile_blk<H, K, TRUNC, KARA>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count, ws_base, tstride,
-                                     ws_bytes, coff, tile0, tile0 + (threadIdx.x & 63u));
+  const uint32_t tbytes = BlkLayout<H, K>::rows(w) * 256u;  // this block's region
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  modexp_tile_blk<H, K, TRUNC, KARA>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
+                                     ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0);
 }
 
 }  // namespace mx

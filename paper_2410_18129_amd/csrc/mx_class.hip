@@ -45,7 +45,7 @@ hipError_t mont_fn(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint
     if (impl == 2) {
 #define MX_L(T, S)                                                                                                \
   hipLaunchKernelGGL((k_mont_blk<kH, kK, T, S, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count, \
-                     ws, tstride, ws_bytes, coff)
+                     ws, ws_bytes, coff)
       if (trunc) {
         if (sqr) MX_L(true, true); else MX_L(true, false);
       } else {
@@ -59,7 +59,7 @@ hipError_t mont_fn(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint
     if (kBlock || impl == 1) {
 #define MX_L(T, S)                                                                                              \
   hipLaunchKernelGGL((k_mont_blk<kH, kK, T, S>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count, ws, \
-                     tstride, ws_bytes, coff)
+                     ws_bytes, coff)
       if (trunc) {
         if (sqr) MX_L(true, true); else MX_L(true, false);
       } else {
@@ -88,15 +88,18 @@ hipError_t mont_fn(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint
 hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base, const uint64_t* ex,
                      uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out, uint32_t count, uint32_t* ws,
                      uint32_t tstride, uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
+  // each block works in its own tile region of ws (ws_rows x 64 words); tstride,
+  // the launch width padded to 64, only sized ws
+  (void)tstride;
   const uint32_t blocks = (count + 63) / 64;
   if constexpr (kHasKara) {
     if (impl == 2) {
       if (trunc)
         hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex,
-                           ebits, ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+                           ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
       else
         hipLaunchKernelGGL((k_modexp_blk<kH, kK, false, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex,
-                           ebits, ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+                           ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
       return hipGetLastError();
     }
   }
@@ -104,20 +107,20 @@ hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* ci
     if (kBlock || impl == 1) {
       if (trunc)
         hipLaunchKernelGGL((k_modexp_blk<kH, kK, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
-                           ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+                           ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
       else
         hipLaunchKernelGGL((k_modexp_blk<kH, kK, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex,
-                           ebits, ewords, w, (uint32_t)kW, out, count, ws, tstride, ws_bytes, coff);
+                           ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
       return hipGetLastError();
     }
   }
   if constexpr (!kBlock) {
     if (trunc)
       hipLaunchKernelGGL((k_modexp<kN, kW, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits, ewords,
-                         w, out, count, ws, tstride, ws_bytes, coff);
+                         w, out, count, ws, ws_bytes, coff);
     else
       hipLaunchKernelGGL((k_modexp<kN, kW, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
-                         ewords, w, out, count, ws, tstride, ws_bytes, coff);
+                         ewords, w, out, count, ws, ws_bytes, coff);
   }
   return hipGetLastError();
 }

@@ -38,23 +38,107 @@ __device__ __forceinline__ void sfor(F&& f) {
   if constexpr (E > B) sfor_impl<B>(f, std::make_integer_sequence<int, E - B>{});
 }
 
-__device__ __forceinline__ uint64_t mac(uint64_t acc, uint32_t a, uint32_t b) {
-  return acc + (uint64_t)a * (uint64_t)b;  // v_mad_u64_u32
+// ---- partial products ----------------------------------------------------
+//
+// One 28x28-bit partial product into a 64-bit column sum is one
+// v_mad_u64_u32 (acc + a * b).  mad8 is eight products sharing one
+// multiplier (eight independent accumulators), mac a single product.
+__device__ __forceinline__ void mac(uint64_t& acc, uint32_t a, uint32_t b) { acc += (uint64_t)a * (uint64_t)b; }
+
+// acc[d] += x_d * v for d = 0..7.
+__device__ __forceinline__ void mad8(uint64_t (&acc)[8], uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                     uint32_t x4, uint32_t x5, uint32_t x6, uint32_t x7, uint32_t v) {
+  mac(acc[0], x0, v);
+  mac(acc[1], x1, v);
+  mac(acc[2], x2, v);
+  mac(acc[3], x3, v);
+  mac(acc[4], x4, v);
+  mac(acc[5], x5, v);
+  mac(acc[6], x6, v);
+  mac(acc[7], x7, v);
 }
 
-// sum_{i=LO..HI} a[i] * b[K-i], two interleaved chains for issue overlap.
-template <int K, int LO, int HI, int NA, int NB>
-__device__ __forceinline__ uint64_t colsum(const uint32_t (&a)[NA], const uint32_t (&b)[NB]) {
-  uint64_t s0 = 0, s1 = 0;
-  sfor<LO, HI + 1>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    static_assert(i >= 0 && i < NA && K - i >= 0 && K - i < NB, "column index");
-    if constexpr (((i - LO) & 1) == 0)
-      s0 = mac(s0, a[i], b[K - i]);
-    else
-      s1 = mac(s1, a[i], b[K - i]);
+// ---- column blocks ---------------------------------------------------------
+//
+// Every product below is formed BK = 8 columns at a time: for the columns
+// K0 .. K0+BK-1 and each limb index j of the second operand,
+// acc[d] += a[K0 + d - j] * b[j], so one word of the second operand feeds up
+// to eight products (one mad8 where all eight lie inside the bounds).  b is
+// in registers or, for the modulus and N', in LDS.  The accumulators of one
+// block are then normalised into limbs; a compiler barrier between blocks
+// keeps the loaded words short-lived instead of letting them pile up in
+// registers.
+constexpr int kColBlock = 8;
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+// The products of one word v = (second operand)[j] with the first operand for
+// the columns K0 .. K0+BK-1: acc[d] += a[K0 + d - j] * v wherever
+// ILO <= K0 + d - j <= IHI and, when UPPER, K0 + d - j > j (each off-diagonal
+// pair of a square once).
+template <int K0, int BK, int ILO, int IHI, bool UPPER, int J, int NA>
+__device__ __forceinline__ void colstep(const uint32_t (&a)[NA], uint32_t v, uint64_t (&acc)[BK]) {
+  constexpr auto ok = [](int d) {
+    const int i = K0 + d - J;
+    return i >= ILO && i <= IHI && (!UPPER || i > J);
+  };
+  constexpr bool full = BK == 8 && ok(0) && ok(1) && ok(2) && ok(3) && ok(4) && ok(5) && ok(6) && ok(7);
+  if constexpr (full) {  // BK == 8: acc is the eight accumulators
+    static_assert(K0 - J >= 0 && K0 + 7 - J < NA, "column index");
+    mad8(*reinterpret_cast<uint64_t(*)[8]>(&acc[0]), a[K0 - J], a[K0 + 1 - J], a[K0 + 2 - J], a[K0 + 3 - J],
+         a[K0 + 4 - J], a[K0 + 5 - J], a[K0 + 6 - J], a[K0 + 7 - J], v);
+  } else {
+    sfor<0, BK>([&](auto D) {
+      constexpr int d = decltype(D)::value;
+      if constexpr (ok(d)) mac(acc[d], a[K0 + d - J], v);
+    });
+  }
+}
+
+// acc[d] += sum over i of a[i] * b[K0 + d - i] for the columns K0 .. K0+BK-1,
+// restricted to ILO <= i <= IHI (and i > K0 + d - i when UPPER); b in registers.
+template <int K0, int BK, int ILO, int IHI, int JLO, int JHI, bool UPPER = false, int NA, int NB>
+__device__ __forceinline__ void colblock(const uint32_t (&a)[NA], const uint32_t (&b)[NB], uint64_t (&acc)[BK]) {
+  constexpr int jmin = (K0 - IHI) > JLO ? (K0 - IHI) : JLO;
+  constexpr int jmax = (K0 + BK - 1 - ILO) < JHI ? (K0 + BK - 1 - ILO) : JHI;
+  sfor<jmin, jmax + 1>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    colstep<K0, BK, ILO, IHI, UPPER, j>(a, b[j], acc);
   });
-  return s0 + s1;
+}
+
+// As colblock, with the words of the second operand read from memory (LDS)
+// by ld(j).  They are read in groups of kPrefetch words, one group ahead of
+// the products that use them, so that the latency of a group's reads is
+// covered by the previous group's products (one wavefront per SIMD has no
+// other wavefront to switch to).
+constexpr int kPrefetch = 8;
+
+template <int K0, int BK, int ILO, int IHI, int JLO, int JHI, int NA, typename Ld>
+__device__ __forceinline__ void colblock_ld(const uint32_t (&a)[NA], Ld&& ld, uint64_t (&acc)[BK]) {
+  constexpr int jmin = (K0 - IHI) > JLO ? (K0 - IHI) : JLO;
+  constexpr int jmax = (K0 + BK - 1 - ILO) < JHI ? (K0 + BK - 1 - ILO) : JHI;
+  constexpr int G = kPrefetch;
+  constexpr int NG = jmax >= jmin ? (jmax - jmin + G) / G : 0;
+  uint32_t buf[2][G];
+  sfor<0, (NG > 0 ? G : 0)>([&](auto U) {
+    constexpr int j = jmin + decltype(U)::value;
+    if constexpr (j <= jmax) buf[0][decltype(U)::value] = ld(j);
+  });
+  sfor<0, NG>([&](auto GG) {
+    constexpr int g = decltype(GG)::value;
+    if constexpr (g + 1 < NG) {
+      sfor<0, G>([&](auto U) {
+        constexpr int j = jmin + (g + 1) * G + decltype(U)::value;
+        if constexpr (j <= jmax) buf[(g + 1) & 1][decltype(U)::value] = ld(j);
+      });
+    }
+    compiler_fence();  // the next group's reads are issued before this group's products
+    sfor<0, G>([&](auto U) {
+      constexpr int j = jmin + g * G + decltype(U)::value;
+      if constexpr (j <= jmax) colstep<K0, BK, ILO, IHI, false, j>(a, buf[g & 1][decltype(U)::value], acc);
+    });
+  });
 }
 
 // ---- products (Section 2 / Algorithms 1 and 2) ----------------------------
@@ -62,14 +146,21 @@ __device__ __forceinline__ uint64_t colsum(const uint32_t (&a)[NA], const uint32
 // t = a * b, 2N normalised limbs.
 template <int N>
 __device__ __forceinline__ void mul_sb(const uint32_t (&a)[N], const uint32_t (&b)[N], uint32_t (&t)[2 * N]) {
+  constexpr int BK = kColBlock;
   uint64_t carry = 0;
-  sfor<0, 2 * N - 1>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    constexpr int lo = k > N - 1 ? k - (N - 1) : 0;
-    constexpr int hi = k < N - 1 ? k : N - 1;
-    uint64_t acc = colsum<k, lo, hi>(a, b) + carry;
-    t[k] = (uint32_t)acc & kLimbMask;
-    carry = acc >> kLimbBits;
+  sfor<0, (2 * N - 1 + BK - 1) / BK>([&](auto B) {
+    constexpr int k0 = decltype(B)::value * BK;
+    constexpr int bk = (2 * N - 1 - k0) < BK ? (2 * N - 1 - k0) : BK;
+    uint64_t acc[bk];
+    sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
+    colblock<k0, bk, 0, N - 1, 0, N - 1>(a, b, acc);
+    sfor<0, bk>([&](auto D) {
+      constexpr int d = decltype(D)::value;
+      const uint64_t v = acc[d] + carry;
+      t[k0 + d] = (uint32_t)v & kLimbMask;
+      carry = v >> kLimbBits;
+    });
+    compiler_fence();
   });
   t[2 * N - 1] = (uint32_t)carry;
 }
@@ -77,15 +168,24 @@ __device__ __forceinline__ void mul_sb(const uint32_t (&a)[N], const uint32_t (&
 // t = a^2: off-diagonal products once, doubled, plus the diagonal (Algorithm 2).
 template <int N>
 __device__ __forceinline__ void sqr_sb(const uint32_t (&a)[N], uint32_t (&t)[2 * N]) {
+  constexpr int BK = kColBlock;
   uint64_t carry = 0;
-  sfor<0, 2 * N - 1>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    constexpr int lo = k > N - 1 ? k - (N - 1) : 0;
-    constexpr int hi = (k + 1) / 2 - 1;  // i < k - i
-    uint64_t acc = (colsum<k, lo, hi>(a, a) << 1) + carry;
-    if constexpr ((k & 1) == 0) acc = mac(acc, a[k / 2], a[k / 2]);
-    t[k] = (uint32_t)acc & kLimbMask;
-    carry = acc >> kLimbBits;
+  sfor<0, (2 * N - 1 + BK - 1) / BK>([&](auto B) {
+    constexpr int k0 = decltype(B)::value * BK;
+    constexpr int bk = (2 * N - 1 - k0) < BK ? (2 * N - 1 - k0) : BK;
+    uint64_t acc[bk];
+    sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
+    colblock<k0, bk, 0, N - 1, 0, N - 1, true>(a, a, acc);
+    sfor<0, bk>([&](auto D) {
+      constexpr int d = decltype(D)::value;
+      constexpr int k = k0 + d;
+      uint64_t v = acc[d] << 1;
+      if constexpr ((k & 1) == 0) mac(v, a[k / 2], a[k / 2]);
+      v += carry;
+      t[k] = (uint32_t)v & kLimbMask;
+      carry = v >> kLimbBits;
+    });
+    compiler_fence();
   });
   t[2 * N - 1] = (uint32_t)carry;
 }
@@ -105,74 +205,9 @@ __device__ __forceinline__ void sqr_sb(const uint32_t (&a)[N], uint32_t (&t)[2 *
 //   carry out of the low n limbs is propagated.
 // C = floor(T / R) + sum_{w >= n} P_w 2^{28 (w - n)} + k   (Algorithm 6, step 4)
 //
-// `mod` and `np` are read from memory limb by limb (column-major per lane).
-template <int N, bool TRUNC, typename LoadM, typename LoadNP>
-__device__ __forceinline__ void redc(const uint32_t (&t)[2 * N], LoadM&& ldm, LoadNP&& ldnp, uint32_t (&c)[N]) {
-  static_assert(N >= 3, "size class too small");
-  uint32_t q[N];
-  {
-    uint32_t np[N];
-    sfor<0, N>([&](auto I) { np[decltype(I)::value] = ldnp(decltype(I)::value); });
-    uint64_t carry = 0;
-    sfor<0, N>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      uint64_t acc = colsum<k, 0, k>(t, np) + carry;
-      q[k] = (uint32_t)acc & kLimbMask;
-      carry = acc >> kLimbBits;
-    });
-  }
-  uint32_t m[N];
-  sfor<0, N>([&](auto I) { m[decltype(I)::value] = ldm(decltype(I)::value); });
-  uint64_t carry;
-  if constexpr (TRUNC) {
-    const uint64_t a2 = colsum<N - 2, 0, N - 2>(q, m) + t[N - 2];
-    const uint64_t a1 = colsum<N - 1, 0, N - 1>(q, m) + t[N - 1] + (a2 >> kLimbBits);
-    carry = (a1 >> kLimbBits) + ((((uint32_t)a1 | (uint32_t)a2) & kLimbMask) != 0u ? 1u : 0u);
-  } else {
-    carry = 0;
-    sfor<0, N>([&](auto W) {
-      constexpr int w = decltype(W)::value;
-      uint64_t acc = colsum<w, 0, w>(q, m) + t[w] + carry;
-      carry = acc >> kLimbBits;  // low 28 bits are zero: T + qN = 0 mod R
-    });
-  }
-  sfor<N, 2 * N - 1>([&](auto W) {
-    constexpr int w = decltype(W)::value;
-    uint64_t acc = colsum<w, w - (N - 1), N - 1>(q, m) + t[w] + carry;
-    c[w - N] = (uint32_t)acc & kLimbMask;
-    carry = acc >> kLimbBits;
-  });
-  c[N - 1] = (uint32_t)(carry + t[2 * N - 1]);
-}
-
-// ---- reduction with N and N' staged in LDS --------------------------------
-//
-// Same arithmetic as redc() above; the modulus limbs m[j] and N' limbs np[j]
-// come from LDS (lane-private columns, [limb][lane]: consecutive lanes hit
-// consecutive banks).  Columns are formed BK at a time so every LDS word
-// read feeds up to BK products; a compiler barrier between blocks keeps the
-// loaded words short-lived instead of letting them pile up in registers.
-constexpr int kColBlock = 8;
-
-__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
-
-// acc[d] += sum over i of a[i] * ld(K0 + d - i) for the columns K0 .. K0+BK-1,
-// restricted to ILO <= i <= IHI and JLO <= K0 + d - i <= JHI.
-template <int K0, int BK, int ILO, int IHI, int JLO, int JHI, int NA, typename Ld>
-__device__ __forceinline__ void colblock(const uint32_t (&a)[NA], Ld&& ld, uint64_t (&acc)[BK]) {
-  constexpr int jmin = (K0 - IHI) > JLO ? (K0 - IHI) : JLO;
-  constexpr int jmax = (K0 + BK - 1 - ILO) < JHI ? (K0 + BK - 1 - ILO) : JHI;
-  sfor<jmin, jmax + 1>([&](auto J) {
-    constexpr int j = decltype(J)::value;
-    const uint32_t v = ld(j);
-    sfor<0, BK>([&](auto D) {
-      constexpr int d = decltype(D)::value;
-      constexpr int i = K0 + d - j;
-      if constexpr (i >= ILO && i <= IHI) acc[d] = mac(acc[d], a[i], v);
-    });
-  });
-}
-
+// The modulus limbs m[j] and N' limbs np[j] come from LDS (lane-private
+// columns, [limb][lane]: consecutive lanes hit consecutive banks) through
+// ldm / ldnp; each word read feeds up to eight products.
 template <int N, bool TRUNC, typename LoadM, typename LoadNP>
 __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm, LoadNP&& ldnp, uint32_t (&c)[N]) {
   static_assert(N >= 3, "size class too small");
@@ -185,7 +220,7 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
     constexpr int bk = (N - k0) < BK ? (N - k0) : BK;
     uint64_t acc[bk];
     sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
-    colblock<k0, bk, 0, N - 1, 0, N - 1>(t, ldnp, acc);
+    colblock_ld<k0, bk, 0, N - 1, 0, N - 1>(t, ldnp, acc);
     sfor<0, bk>([&](auto D) {
       constexpr int d = decltype(D)::value;
       const uint64_t v = acc[d] + carry;
@@ -204,7 +239,7 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
     constexpr int bk = (2 * N - 1 - w0) < BK ? (2 * N - 1 - w0) : BK;
     uint64_t acc[bk];
     sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = t[w0 + decltype(D)::value]; });
-    colblock<w0, bk, 0, N - 1, 0, N - 1>(q, ldm, acc);
+    colblock_ld<w0, bk, 0, N - 1, 0, N - 1>(q, ldm, acc);
     sfor<0, bk>([&](auto D) {
       constexpr int d = decltype(D)::value;
       constexpr int w = w0 + d;
@@ -231,12 +266,21 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
 // r = a * b mod 2^(28 H): the low half of the product (Algorithm 6 step 1 on a block).
 template <int H>
 __device__ __forceinline__ void lo_sb(const uint32_t (&a)[H], const uint32_t (&b)[H], uint32_t (&r)[H]) {
+  constexpr int BK = kColBlock;
   uint64_t carry = 0;
-  sfor<0, H>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    uint64_t acc = colsum<k, 0, k>(a, b) + carry;
-    r[k] = (uint32_t)acc & kLimbMask;
-    carry = acc >> kLimbBits;
+  sfor<0, (H + BK - 1) / BK>([&](auto B) {
+    constexpr int k0 = decltype(B)::value * BK;
+    constexpr int bk = (H - k0) < BK ? (H - k0) : BK;
+    uint64_t acc[bk];
+    sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
+    colblock<k0, bk, 0, H - 1, 0, H - 1>(a, b, acc);
+    sfor<0, bk>([&](auto D) {
+      constexpr int d = decltype(D)::value;
+      const uint64_t v = acc[d] + carry;
+      r[k0 + d] = (uint32_t)v & kLimbMask;
+      carry = v >> kLimbBits;
+    });
+    compiler_fence();
   });
 }
 
@@ -245,14 +289,22 @@ __device__ __forceinline__ void lo_sb(const uint32_t (&a)[H], const uint32_t (&b
 // products of Theorem 2 that a block contributes at or above column n - 2.
 template <int H>
 __device__ __forceinline__ void hi_sb(const uint32_t (&a)[H], const uint32_t (&b)[H], uint32_t (&v)[H + 2]) {
+  constexpr int BK = kColBlock;
+  constexpr int W0 = H - 2, NCOL = 2 * H - 1 - W0;
   uint64_t carry = 0;
-  sfor<H - 2, 2 * H - 1>([&](auto W) {
-    constexpr int w = decltype(W)::value;
-    constexpr int lo = w > H - 1 ? w - (H - 1) : 0;
-    constexpr int hi = w < H - 1 ? w : H - 1;
-    uint64_t acc = colsum<w, lo, hi>(a, b) + carry;
-    v[w - (H - 2)] = (uint32_t)acc & kLimbMask;
-    carry = acc >> kLimbBits;
+  sfor<0, (NCOL + BK - 1) / BK>([&](auto B) {
+    constexpr int w0 = W0 + decltype(B)::value * BK;
+    constexpr int bk = (2 * H - 1 - w0) < BK ? (2 * H - 1 - w0) : BK;
+    uint64_t acc[bk];
+    sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
+    colblock<w0, bk, 0, H - 1, 0, H - 1>(a, b, acc);
+    sfor<0, bk>([&](auto D) {
+      constexpr int d = decltype(D)::value;
+      const uint64_t x = acc[d] + carry;
+      v[w0 + d - W0] = (uint32_t)x & kLimbMask;
+      carry = x >> kLimbBits;
+    });
+    compiler_fence();
   });
   v[H + 1] = (uint32_t)carry;
 }

@@ -152,18 +152,34 @@ __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restr
 // multiplication code and the reduction each exist once in the binary.
 enum StepKind : int { kSqr = 0, kMulR2 = 1, kMulG1 = 2, kMulSel = 3, kMulOne = 4, kLoadSel = 5 };
 
+// Start-phase stagger.  Every wavefront runs the same schedule at the same
+// speed, so without it the table scans of all wavefronts (the one phase that
+// streams memory) coincide and the memory system idles during the squarings.
+// Wavefront groups (consecutive blocks go to different XCDs, so the groups
+// are taken over blocks / 8) start a quarter of a window period apart, about
+// 3 (w + 1) N^2 cycles: (w + 1) Montgomery operations of about 2 N^2 products
+// at about 6 cycles each.  s_sleep(127) waits 127 x 64 cycles.
+template <int N>
+__device__ __forceinline__ void stagger(uint32_t block, uint32_t w) {
+  const uint32_t phase = (block >> 3) & 3u;
+  const uint32_t naps = phase * ((w + 1u) * 3u * (uint32_t)(N * N) / (127u * 64u));
+  for (uint32_t i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(127);
+}
+
 // Modular exponentiation of one tile of 64 instances (one wavefront).
 // tile0: first instance of the tile; lane l handles instance tile0 + l (the
 // lanes past `count` recompute the last instance and store nothing).
-// wcol: this lane's column in the workspace (table rows of tstride columns).
+// table: this wavefront's own workspace region of tbytes >= 2^w N 256 bytes,
+// limb-major over its 64 lanes (entry e, limb i of lane l at byte
+// (e N + i) 256 + 4 l), so that every read of the table scan is a whole
+// 256-byte row and a wavefront's table is one contiguous range of memory.
 // s_ctx: 2 N 64 words of LDS for the lane's N and N'.
 template <int N, int BW, bool TRUNC>
 __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
                                             const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                             uint32_t ebits, uint32_t ewords, uint32_t w,
                                             uint64_t* __restrict__ out, uint32_t count, uint32_t* __restrict__ table,
-                                            uint32_t tstride, uint32_t tbytes, uint32_t coff, uint32_t tile0,
-                                            uint32_t wcol, uint32_t* s_ctx) {
+                                            uint32_t tbytes, uint32_t coff, uint32_t tile0, uint32_t* s_ctx) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t gid = tile0 + lane;
   const bool live = gid < count;
@@ -173,10 +189,9 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
   const uint32_t* cn = ctx.n + c;
   const uint32_t* cnp = ctx.np + c;
   const size_t cs = ctx.stride;
-  // table: entry e, limb i of this lane at byte (e * N + i) * tstride * 4 + wcol * 4
   const __amdgpu_buffer_rsrc_t tr = make_buf(table, tbytes);
-  const uint32_t tvo = wcol * 4u;
-  const uint32_t tls = tstride * 4u;  // bytes between consecutive limbs
+  const uint32_t tvo = lane * 4u;
+  const uint32_t tls = 256u;  // bytes between consecutive limbs
   const uint64_t* e64 = ex + (size_t)inst * ewords;
 
   const uint32_t nent = 1u << w;
@@ -283,17 +298,20 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
   if (live) contract<N, BW>(y, out + (size_t)inst * BW);
 }
 
+// ws: ceil(count / 64) tile regions of 2^w N 256 bytes each, one per block.
 template <int N, int BW, bool TRUNC>
 __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                uint32_t ebits, uint32_t ewords, uint32_t w,
-                                               uint64_t* __restrict__ out, uint32_t count,
-                                               uint32_t* __restrict__ table, uint32_t tstride, uint32_t tbytes,
-                                               uint32_t coff) {
+                                               uint64_t* __restrict__ out, uint32_t count, uint32_t* __restrict__ ws,
+                                               uint32_t ws_bytes, uint32_t coff) {
   __shared__ uint32_t s_ctx[2 * N * 64];
   const uint32_t tile0 = blockIdx.x * 64;
-  modexp_tile<N, BW, TRUNC>(ctx, cidx, base, ex, ebits, ewords, w, out, count, table, tstride, tbytes, coff, tile0,
-                            tile0 + (threadIdx.x & 63u), s_ctx);
+  const uint32_t tbytes = (1u << w) * (uint32_t)N * 256u;
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  stagger<N>(blockIdx.x, w);
+  modexp_tile<N, BW, TRUNC>(ctx, cidx, base, ex, ebits, ewords, w, out, count, ws + (size_t)blockIdx.x * (tbytes / 4u),
+                            tbytes, coff, tile0, s_ctx);
 }
 
 

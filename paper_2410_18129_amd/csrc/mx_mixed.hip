@@ -39,8 +39,8 @@ struct MixedBatch {
   const uint64_t* base;
   const uint64_t* ex;
   uint64_t* out;
-  uint32_t* ws;
-  uint32_t count, ebits, ewords, w, family, ws_bytes;
+  uint32_t* ws;   // one region of rows x 64 words per persistent wave
+  uint32_t count, ebits, ewords, w, family, rows;
 };
 
 struct MixedArgs {
@@ -48,7 +48,6 @@ struct MixedArgs {
   const uint32_t* jobs;  // batch index << 28 | tile index
   uint32_t* counter;
   uint32_t njobs;
-  uint32_t tstride;  // workspace columns: persistent waves x 64
 };
 
 __global__ void k_reset_counter(uint32_t* counter) {
@@ -58,7 +57,6 @@ __global__ void k_reset_counter(uint32_t* counter) {
 __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
   __shared__ uint32_t s_ctx[2 * 74 * 64];  // N, N' staging of the largest register-resident class
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wcol = blockIdx.x * 64u + lane;
   for (;;) {
     uint32_t j = 0;
     if (lane == 0) j = atomicAdd(args.counter, 1u);
@@ -67,39 +65,40 @@ __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
     const uint32_t job = args.jobs[j];
     const MixedBatch& mb = args.b[job >> 28];
     const uint32_t tile0 = (job & 0x0FFFFFFFu) * 64u;
-    const uint32_t ts = args.tstride;
+    const uint32_t tb = mb.rows * 256u;                         // this wave's region of the batch's workspace
+    uint32_t* const tw = mb.ws + (size_t)blockIdx.x * (tb / 4u);
     switch (mb.family) {
       case kF1024:
         modexp_tile<37, 16, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, mb.out, mb.count,
-                                  mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol, s_ctx);
+                                  tw, tb, 0u, tile0, s_ctx);
         break;
       case kF1024B:
         modexp_tile_blk<37, 1, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 16u, mb.out,
-                                     mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
+                                     mb.count, tw, tb, 0u, tile0);
         break;
       case kF2048:
         modexp_tile<74, 32, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, mb.out, mb.count,
-                                  mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol, s_ctx);
+                                  tw, tb, 0u, tile0, s_ctx);
         break;
       case kF2048B:
         modexp_tile_blk<37, 2, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 32u, mb.out,
-                                     mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
+                                     mb.count, tw, tb, 0u, tile0);
         break;
       case kF3072B:
         modexp_tile_blk<37, 3, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 48u, mb.out,
-                                     mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
+                                     mb.count, tw, tb, 0u, tile0);
         break;
       case kF2048K:
         modexp_tile_blk<37, 2, true, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 32u, mb.out,
-                                           mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
+                                           mb.count, tw, tb, 0u, tile0);
         break;
       case kF4096K:
         modexp_tile_blk<37, 4, true, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u, mb.out,
-                                           mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
+                                           mb.count, tw, tb, 0u, tile0);
         break;
       default:
         modexp_tile_blk<37, 4, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u, mb.out,
-                                     mb.count, mb.ws, ts, mb.ws_bytes, 0u, tile0, wcol);
+                                     mb.count, tw, tb, 0u, tile0);
         break;
     }
   }
@@ -189,7 +188,6 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
   p->nbatch = nbatch;
   p->njobs = (uint32_t)total_tiles;
   p->nslots = (uint32_t)std::min<uint64_t>((uint64_t)cus * 4u, std::max<uint64_t>(total_tiles, 1));
-  p->args.tstride = p->nslots * 64u;
   p->args.njobs = p->njobs;
   hipError_t e = hipSuccess;
   // jobs: every tile of every batch, the costliest first
@@ -206,7 +204,7 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     const uint32_t w = d.window ? d.window : (c->bits <= 2048 ? 3u : 5u);
     const int impl = (d.flags & MX_MUL_KARATSUBA) ? 2 : ((d.flags & MX_IMPL_BLOCK) || c->bits > 2048 ? 1 : 0);
     const uint32_t rows = c->ops->ws_rows(impl, true, w);
-    const size_t bytes = (size_t)rows * p->args.tstride * sizeof(uint32_t);
+    const size_t bytes = (size_t)rows * p->nslots * 64u * sizeof(uint32_t);
     if (bytes > mx::kMaxWsBytes) {
       delete p;
       return mx_fail(MX_EUNSUPPORTED, "batch %u: window %u needs %zu workspace bytes (> 2 GiB); use a smaller window",
@@ -225,7 +223,7 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     mb.ewords = (d.exp_bits + 63) / 64;
     mb.w = w;
     mb.family = fam[b];
-    mb.ws_bytes = (uint32_t)bytes;
+    mb.rows = rows;
     const float est = (float)c->limbs * c->limbs * (float)(d.exp_bits ? d.exp_bits : 1);
     const float cost = d.tile_cost > 0.f ? d.tile_cost : est;
     for (uint32_t t = 0; t < (d.n + 63) / 64; ++t) tiles.push_back({cost, (b << 28) | t});

@@ -67,12 +67,20 @@ class Trace:
 
 
 class Server:
-    """Continuous-batching scheduler (see the module docstring)."""
+    """Continuous-batching scheduler (see the module docstring).
 
-    def __init__(self, executor, classes, max_batch, idle_sleep=20e-6):
+    Pacing: a batch costs about the same time whatever its size (every lane
+    runs one whole exponentiation), so a class with k slots starts a new batch
+    at most every (observed batch duration) / k seconds, unless a full batch is
+    waiting.  Without pacing, a trickle of arrivals would occupy every slot
+    with a tiny batch and the next arrivals would wait a whole batch duration.
+    """
+
+    def __init__(self, executor, classes, max_batch, idle_sleep=20e-6, pace=True):
         self.ex, self.classes = executor, tuple(classes)
         self.max_batch = dict(max_batch)
         self.idle_sleep = idle_sleep
+        self.pace = pace
 
     def run(self, trace, timeout_s=600.0):
         """Replays the trace in real time; returns per-request finish times and status."""
@@ -82,7 +90,10 @@ class Server:
         batches = []  # (cls, lo, hi, launch time)
         head = {c: 0 for c in self.classes}  # next request (class numbering) not yet launched
         free = {c: deque(self.ex.slots(c)) for c in self.classes}
-        busy = []  # (slot, cls, lo, hi)
+        nslot = {c: max(1, len(free[c])) for c in self.classes}
+        dur = {c: 0.0 for c in self.classes}  # running estimate of a batch's duration per class
+        last = {c: -1e30 for c in self.classes}  # launch time of the class's latest batch
+        busy = []  # (slot, cls, lo, hi, launch time)
         # global request ids of class c in class order, to write finish times
         gid = {c: np.nonzero(trace.cls == c)[0] for c in self.classes}
         done = 0
@@ -96,12 +107,13 @@ class Server:
             progressed = False
             # retire finished batches
             still = []
-            for slot, c, lo, hi in busy:
+            for slot, c, lo, hi, tl in busy:
                 st = self.ex.poll(slot)
                 if st is None:
-                    still.append((slot, c, lo, hi))
+                    still.append((slot, c, lo, hi, tl))
                     continue
                 t = time.perf_counter() - t0
+                dur[c] = t - tl if dur[c] == 0.0 else 0.7 * dur[c] + 0.3 * (t - tl)
                 ids = gid[c][lo:hi]
                 finish[ids] = t
                 if st is not True:
@@ -120,6 +132,9 @@ class Server:
                 while free[c] and arrived > head[c]:
                     lo = head[c]
                     hi = min(arrived, lo + self.max_batch[c])
+                    if (self.pace and hi - lo < self.max_batch[c] and
+                            time.perf_counter() - t0 - last[c] < dur[c] / nslot[c]):
+                        break
                     slot = free[c].popleft()
                     try:
                         self.ex.launch(slot, c, lo, hi)
@@ -131,8 +146,10 @@ class Server:
                         free[c].append(slot)
                         head[c] = hi
                         continue
-                    busy.append((slot, c, lo, hi))
-                    batches.append((c, lo, hi, time.perf_counter() - t0))
+                    tl = time.perf_counter() - t0
+                    busy.append((slot, c, lo, hi, tl))
+                    batches.append((c, lo, hi, tl))
+                    last[c] = tl
                     head[c] = hi
                     progressed = True
             if not progressed:
@@ -153,9 +170,10 @@ class ServeResult:
         lat = (self.finish - tr.arrival)[ok]
         span = np.nanmax(self.finish[k0:]) - tr.arrival[k0] if tr.n > k0 else float("nan")
         sizes = [hi - lo for _, lo, hi, _ in self.batches]
-        return {
+        out = {
             "offered_rate": tr.rate,
             "requests": int(ok.sum()),
+            "arrival_span_s": float(tr.arrival[-1]) if tr.n else 0.0,
             "throughput": float(ok.sum() / span) if span > 0 else float("nan"),
             "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else float("nan"),
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else float("nan"),
@@ -164,6 +182,18 @@ class ServeResult:
             "mean_batch": float(np.mean(sizes)) if sizes else 0.0,
             "failed": int(self.failed.sum()),
         }
+        all_lat = self.finish - tr.arrival
+        for c in tr.classes:
+            m = ok & (tr.cls == c)
+            if m.any():
+                out["p50_ms_%d" % c] = float(np.percentile(all_lat[m], 50) * 1e3)
+                out["p99_ms_%d" % c] = float(np.percentile(all_lat[m], 99) * 1e3)
+        return out
+
+
+def hw_queues_needed(classes, max_slots):
+    """One hardware queue per execution slot, plus the default stream's."""
+    return len(tuple(classes)) * max_slots + 1
 
 
 class GpuExecutor:
@@ -171,7 +201,12 @@ class GpuExecutor:
 
     Contexts: one per class holding that class's moduli (resident for the run).
     Slots: preallocated workspaces (and a stream each), as many per class as
-    the memory budget allows, at most ``max_slots`` per class.
+    the memory budget allows, at most ``max_slots`` per class.  Batches on
+    different streams run concurrently only on different hardware queues:
+    HIP's GPU_MAX_HW_QUEUES (read once, when the process first initialises
+    the device) must be at least ``hw_queues_needed(classes, max_slots)``, or
+    a short batch can wait behind a long one of another class on a shared
+    queue.
     """
 
     def __init__(self, trace, max_batch, mem_budget, windows=None, max_slots=4, device="cuda"):

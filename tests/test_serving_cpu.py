@@ -123,3 +123,19 @@ def test_failures_are_isolated():
     assert not np.isnan(res.finish).any()  # the server kept serving and drained
     ok_classes_results = sum(r is not None for c in CLASSES for r in ex.results[c])
     assert ok_classes_results == int((~res.failed).sum())
+
+
+def test_pacing_staggers_batches_of_a_class():
+    # batches cost a fixed 20 ms whatever their size; with 2 slots and a steady trickle of
+    # arrivals, a paced class starts a batch about every 10 ms instead of filling both slots
+    # with tiny batches, and every request is still served once
+    tr = serving.Trace(4000, 40000.0, k=33, classes=(64,), probs=(1.0,), moduli={64: 20})
+    ex = FakeExecutor(tr, slots_per_class=2, per_req_s=0.0, fixed_s=20e-3)
+    res = serving.Server(ex, tr.classes, {64: 100000}).run(tr, timeout_s=60)
+    assert not res.failed.any()
+    starts = np.array(sorted(t0 for _, _, _, t0, _ in ex.log))
+    gaps = np.diff(starts)[2:]  # after the first batches the duration estimate exists
+    assert np.median(gaps) > 8e-3
+    unpaced = FakeExecutor(tr, slots_per_class=2, per_req_s=0.0, fixed_s=20e-3)
+    serving.Server(unpaced, tr.classes, {64: 100000}, pace=False).run(tr, timeout_s=60)
+    assert len(ex.log) <= len(unpaced.log)
