@@ -154,15 +154,23 @@ enum StepKind : int { kSqr = 0, kMulR2 = 1, kMulG1 = 2, kMulSel = 3, kMulOne = 4
 
 // Start-phase stagger.  Every wavefront runs the same schedule at the same
 // speed, so without it the table scans of all wavefronts (the one phase that
-// streams memory) coincide and the memory system idles during the squarings.
-// Wavefront groups (consecutive blocks go to different XCDs, so the groups
-// are taken over blocks / 8) start a quarter of a window period apart, about
-// 3 (w + 1) N^2 cycles: (w + 1) Montgomery operations of about 2 N^2 products
-// at about 6 cycles each.  s_sleep(127) waits 127 x 64 cycles.
+// streams memory) coincide, and the four wavefronts of a compute unit compete
+// for its load path at the same moments while it idles during the squarings.
+// Wavefronts start at 16 phases spread over one window period, about
+// 12 (w + 1) N^2 cycles ((w + 1) Montgomery operations of about 2 N^2
+// products at about 6 cycles each): the SIMD a wavefront runs on (read from
+// the HW_ID register) picks a quarter of the period, so the four wavefronts of
+// a compute unit scan at different times, and the block index a sixteenth
+// within it.  s_sleep(127) waits 127 x 64 cycles.
+__device__ __forceinline__ uint32_t simd_id() {
+  // s_getreg_b32 HW_REG_HW_ID (id 4), bits [5:4]: the SIMD of this wavefront
+  return (uint32_t)__builtin_amdgcn_s_getreg(4 | (4 << 6) | ((2 - 1) << 11));
+}
+
 template <int N>
 __device__ __forceinline__ void stagger(uint32_t block, uint32_t w) {
-  const uint32_t phase = (block >> 3) & 3u;
-  const uint32_t naps = phase * ((w + 1u) * 3u * (uint32_t)(N * N) / (127u * 64u));
+  const uint32_t phase = simd_id() * 4u + ((block >> 3) & 3u);
+  const uint32_t naps = phase * ((w + 1u) * 12u * (uint32_t)(N * N) / 16u / (127u * 64u));
   for (uint32_t i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(127);
 }
 
