@@ -41,22 +41,74 @@ __device__ __forceinline__ void sfor(F&& f) {
 // ---- partial products ----------------------------------------------------
 //
 // One 28x28-bit partial product into a 64-bit column sum is one
-// v_mad_u64_u32 (acc + a * b).  mad8 is eight products sharing one
-// multiplier (eight independent accumulators), mac a single product.
-__device__ __forceinline__ void mac(uint64_t& acc, uint32_t a, uint32_t b) { acc += (uint64_t)a * (uint64_t)b; }
+// v_mad_u64_u32 (acc + a * b).  The column routines below take the way the
+// products are issued as a policy M: M::mad8 is eight products sharing one
+// multiplier (eight independent accumulators), M::mac<S> a single product.
+//
+// PlainMad leaves the instructions to the compiler.  v_mad_u64_u32 also
+// writes a carry-out SGPR pair that nothing reads, and the compiler gives
+// every such instruction the same pair; issued back to back by one
+// wavefront, instructions writing the same pair wait on each other (about 9
+// SIMD cycles apart on gfx950 with one wavefront per SIMD, against about 5.8
+// when the carry-outs rotate over 8 pairs).  RotMad issues the products from
+// inline assembly with their carry-outs in s[40:41] .. s[54:55] in turn
+// (declared clobbered, never read).  Which is faster depends on the kernel
+// (it removes the compiler's freedom to schedule the products), so each
+// kernel picks the one measured faster.
+struct PlainMad {
+  template <int S>
+  __device__ __forceinline__ static void mac(uint64_t& acc, uint32_t a, uint32_t b) {
+    acc += (uint64_t)a * (uint64_t)b;
+  }
+  __device__ __forceinline__ static void mad8(uint64_t (&acc)[8], uint32_t x0, uint32_t x1, uint32_t x2,
+                                              uint32_t x3, uint32_t x4, uint32_t x5, uint32_t x6, uint32_t x7,
+                                              uint32_t v) {
+    acc[0] += (uint64_t)x0 * v;
+    acc[1] += (uint64_t)x1 * v;
+    acc[2] += (uint64_t)x2 * v;
+    acc[3] += (uint64_t)x3 * v;
+    acc[4] += (uint64_t)x4 * v;
+    acc[5] += (uint64_t)x5 * v;
+    acc[6] += (uint64_t)x6 * v;
+    acc[7] += (uint64_t)x7 * v;
+  }
+};
 
-// acc[d] += x_d * v for d = 0..7.
-__device__ __forceinline__ void mad8(uint64_t (&acc)[8], uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                     uint32_t x4, uint32_t x5, uint32_t x6, uint32_t x7, uint32_t v) {
-  mac(acc[0], x0, v);
-  mac(acc[1], x1, v);
-  mac(acc[2], x2, v);
-  mac(acc[3], x3, v);
-  mac(acc[4], x4, v);
-  mac(acc[5], x5, v);
-  mac(acc[6], x6, v);
-  mac(acc[7], x7, v);
-}
+#define MX_MAD_SDST(P, LO, HI)                                                                     \
+  if constexpr ((S & 7) == P)                                                                      \
+    asm("v_mad_u64_u32 %0, s[" #LO ":" #HI "], %1, %2, %0" : "+v"(acc) : "v"(a), "v"(b)           \
+        : "s" #LO, "s" #HI);
+struct RotMad {
+  template <int S>
+  __device__ __forceinline__ static void mac(uint64_t& acc, uint32_t a, uint32_t b) {
+    MX_MAD_SDST(0, 40, 41)
+    MX_MAD_SDST(1, 42, 43)
+    MX_MAD_SDST(2, 44, 45)
+    MX_MAD_SDST(3, 46, 47)
+    MX_MAD_SDST(4, 48, 49)
+    MX_MAD_SDST(5, 50, 51)
+    MX_MAD_SDST(6, 52, 53)
+    MX_MAD_SDST(7, 54, 55)
+  }
+  __device__ __forceinline__ static void mad8(uint64_t (&acc)[8], uint32_t x0, uint32_t x1, uint32_t x2,
+                                              uint32_t x3, uint32_t x4, uint32_t x5, uint32_t x6, uint32_t x7,
+                                              uint32_t v) {
+    asm("v_mad_u64_u32 %0, s[40:41], %8, %16, %0\n\t"
+        "v_mad_u64_u32 %1, s[42:43], %9, %16, %1\n\t"
+        "v_mad_u64_u32 %2, s[44:45], %10, %16, %2\n\t"
+        "v_mad_u64_u32 %3, s[46:47], %11, %16, %3\n\t"
+        "v_mad_u64_u32 %4, s[48:49], %12, %16, %4\n\t"
+        "v_mad_u64_u32 %5, s[50:51], %13, %16, %5\n\t"
+        "v_mad_u64_u32 %6, s[52:53], %14, %16, %6\n\t"
+        "v_mad_u64_u32 %7, s[54:55], %15, %16, %7"
+        : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5]), "+v"(acc[6]),
+          "+v"(acc[7])
+        : "v"(x0), "v"(x1), "v"(x2), "v"(x3), "v"(x4), "v"(x5), "v"(x6), "v"(x7), "v"(v)
+        : "s40", "s41", "s42", "s43", "s44", "s45", "s46", "s47", "s48", "s49", "s50", "s51", "s52", "s53", "s54",
+          "s55");
+  }
+};
+#undef MX_MAD_SDST
 
 // ---- column blocks ---------------------------------------------------------
 //
@@ -76,7 +128,7 @@ __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory")
 // the columns K0 .. K0+BK-1: acc[d] += a[K0 + d - j] * v wherever
 // ILO <= K0 + d - j <= IHI and, when UPPER, K0 + d - j > j (each off-diagonal
 // pair of a square once).
-template <int K0, int BK, int ILO, int IHI, bool UPPER, int J, int NA>
+template <int K0, int BK, int ILO, int IHI, bool UPPER, int J, typename M, int NA>
 __device__ __forceinline__ void colstep(const uint32_t (&a)[NA], uint32_t v, uint64_t (&acc)[BK]) {
   constexpr auto ok = [](int d) {
     const int i = K0 + d - J;
@@ -85,25 +137,25 @@ __device__ __forceinline__ void colstep(const uint32_t (&a)[NA], uint32_t v, uin
   constexpr bool full = BK == 8 && ok(0) && ok(1) && ok(2) && ok(3) && ok(4) && ok(5) && ok(6) && ok(7);
   if constexpr (full) {  // BK == 8: acc is the eight accumulators
     static_assert(K0 - J >= 0 && K0 + 7 - J < NA, "column index");
-    mad8(*reinterpret_cast<uint64_t(*)[8]>(&acc[0]), a[K0 - J], a[K0 + 1 - J], a[K0 + 2 - J], a[K0 + 3 - J],
+    M::mad8(*reinterpret_cast<uint64_t(*)[8]>(&acc[0]), a[K0 - J], a[K0 + 1 - J], a[K0 + 2 - J], a[K0 + 3 - J],
          a[K0 + 4 - J], a[K0 + 5 - J], a[K0 + 6 - J], a[K0 + 7 - J], v);
   } else {
     sfor<0, BK>([&](auto D) {
       constexpr int d = decltype(D)::value;
-      if constexpr (ok(d)) mac(acc[d], a[K0 + d - J], v);
+      if constexpr (ok(d)) M::template mac<d>(acc[d], a[K0 + d - J], v);
     });
   }
 }
 
 // acc[d] += sum over i of a[i] * b[K0 + d - i] for the columns K0 .. K0+BK-1,
 // restricted to ILO <= i <= IHI (and i > K0 + d - i when UPPER); b in registers.
-template <int K0, int BK, int ILO, int IHI, int JLO, int JHI, bool UPPER = false, int NA, int NB>
+template <int K0, int BK, int ILO, int IHI, int JLO, int JHI, bool UPPER, typename M, int NA, int NB>
 __device__ __forceinline__ void colblock(const uint32_t (&a)[NA], const uint32_t (&b)[NB], uint64_t (&acc)[BK]) {
   constexpr int jmin = (K0 - IHI) > JLO ? (K0 - IHI) : JLO;
   constexpr int jmax = (K0 + BK - 1 - ILO) < JHI ? (K0 + BK - 1 - ILO) : JHI;
   sfor<jmin, jmax + 1>([&](auto J) {
     constexpr int j = decltype(J)::value;
-    colstep<K0, BK, ILO, IHI, UPPER, j>(a, b[j], acc);
+    colstep<K0, BK, ILO, IHI, UPPER, j, M>(a, b[j], acc);
   });
 }
 
@@ -114,7 +166,7 @@ __device__ __forceinline__ void colblock(const uint32_t (&a)[NA], const uint32_t
 // other wavefront to switch to).
 constexpr int kPrefetch = 8;
 
-template <int K0, int BK, int ILO, int IHI, int JLO, int JHI, int NA, typename Ld>
+template <int K0, int BK, int ILO, int IHI, int JLO, int JHI, typename M, int NA, typename Ld>
 __device__ __forceinline__ void colblock_ld(const uint32_t (&a)[NA], Ld&& ld, uint64_t (&acc)[BK]) {
   constexpr int jmin = (K0 - IHI) > JLO ? (K0 - IHI) : JLO;
   constexpr int jmax = (K0 + BK - 1 - ILO) < JHI ? (K0 + BK - 1 - ILO) : JHI;
@@ -136,7 +188,7 @@ __device__ __forceinline__ void colblock_ld(const uint32_t (&a)[NA], Ld&& ld, ui
     compiler_fence();  // the next group's reads are issued before this group's products
     sfor<0, G>([&](auto U) {
       constexpr int j = jmin + g * G + decltype(U)::value;
-      if constexpr (j <= jmax) colstep<K0, BK, ILO, IHI, false, j>(a, buf[g & 1][decltype(U)::value], acc);
+      if constexpr (j <= jmax) colstep<K0, BK, ILO, IHI, false, j, M>(a, buf[g & 1][decltype(U)::value], acc);
     });
   });
 }
@@ -144,7 +196,7 @@ __device__ __forceinline__ void colblock_ld(const uint32_t (&a)[NA], Ld&& ld, ui
 // ---- products (Section 2 / Algorithms 1 and 2) ----------------------------
 
 // t = a * b, 2N normalised limbs.
-template <int N>
+template <int N, typename M = PlainMad>
 __device__ __forceinline__ void mul_sb(const uint32_t (&a)[N], const uint32_t (&b)[N], uint32_t (&t)[2 * N]) {
   constexpr int BK = kColBlock;
   uint64_t carry = 0;
@@ -153,7 +205,7 @@ __device__ __forceinline__ void mul_sb(const uint32_t (&a)[N], const uint32_t (&
     constexpr int bk = (2 * N - 1 - k0) < BK ? (2 * N - 1 - k0) : BK;
     uint64_t acc[bk];
     sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
-    colblock<k0, bk, 0, N - 1, 0, N - 1>(a, b, acc);
+    colblock<k0, bk, 0, N - 1, 0, N - 1, false, M>(a, b, acc);
     sfor<0, bk>([&](auto D) {
       constexpr int d = decltype(D)::value;
       const uint64_t v = acc[d] + carry;
@@ -166,7 +218,7 @@ __device__ __forceinline__ void mul_sb(const uint32_t (&a)[N], const uint32_t (&
 }
 
 // t = a^2: off-diagonal products once, doubled, plus the diagonal (Algorithm 2).
-template <int N>
+template <int N, typename M = PlainMad>
 __device__ __forceinline__ void sqr_sb(const uint32_t (&a)[N], uint32_t (&t)[2 * N]) {
   constexpr int BK = kColBlock;
   uint64_t carry = 0;
@@ -175,12 +227,12 @@ __device__ __forceinline__ void sqr_sb(const uint32_t (&a)[N], uint32_t (&t)[2 *
     constexpr int bk = (2 * N - 1 - k0) < BK ? (2 * N - 1 - k0) : BK;
     uint64_t acc[bk];
     sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
-    colblock<k0, bk, 0, N - 1, 0, N - 1, true>(a, a, acc);
+    colblock<k0, bk, 0, N - 1, 0, N - 1, true, M>(a, a, acc);
     sfor<0, bk>([&](auto D) {
       constexpr int d = decltype(D)::value;
       constexpr int k = k0 + d;
       uint64_t v = acc[d] << 1;
-      if constexpr ((k & 1) == 0) mac(v, a[k / 2], a[k / 2]);
+      if constexpr ((k & 1) == 0) M::template mac<d>(v, a[k / 2], a[k / 2]);
       v += carry;
       t[k] = (uint32_t)v & kLimbMask;
       carry = v >> kLimbBits;
@@ -208,7 +260,7 @@ __device__ __forceinline__ void sqr_sb(const uint32_t (&a)[N], uint32_t (&t)[2 *
 // The modulus limbs m[j] and N' limbs np[j] come from LDS (lane-private
 // columns, [limb][lane]: consecutive lanes hit consecutive banks) through
 // ldm / ldnp; each word read feeds up to eight products.
-template <int N, bool TRUNC, typename LoadM, typename LoadNP>
+template <int N, bool TRUNC, typename M = PlainMad, typename LoadM, typename LoadNP>
 __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm, LoadNP&& ldnp, uint32_t (&c)[N]) {
   static_assert(N >= 3, "size class too small");
   constexpr int BK = kColBlock;
@@ -220,7 +272,7 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
     constexpr int bk = (N - k0) < BK ? (N - k0) : BK;
     uint64_t acc[bk];
     sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
-    colblock_ld<k0, bk, 0, N - 1, 0, N - 1>(t, ldnp, acc);
+    colblock_ld<k0, bk, 0, N - 1, 0, N - 1, M>(t, ldnp, acc);
     sfor<0, bk>([&](auto D) {
       constexpr int d = decltype(D)::value;
       const uint64_t v = acc[d] + carry;
@@ -239,7 +291,7 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
     constexpr int bk = (2 * N - 1 - w0) < BK ? (2 * N - 1 - w0) : BK;
     uint64_t acc[bk];
     sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = t[w0 + decltype(D)::value]; });
-    colblock_ld<w0, bk, 0, N - 1, 0, N - 1>(q, ldm, acc);
+    colblock_ld<w0, bk, 0, N - 1, 0, N - 1, M>(q, ldm, acc);
     sfor<0, bk>([&](auto D) {
       constexpr int d = decltype(D)::value;
       constexpr int w = w0 + d;
@@ -273,7 +325,7 @@ __device__ __forceinline__ void lo_sb(const uint32_t (&a)[H], const uint32_t (&b
     constexpr int bk = (H - k0) < BK ? (H - k0) : BK;
     uint64_t acc[bk];
     sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
-    colblock<k0, bk, 0, H - 1, 0, H - 1>(a, b, acc);
+    colblock<k0, bk, 0, H - 1, 0, H - 1, false, PlainMad>(a, b, acc);
     sfor<0, bk>([&](auto D) {
       constexpr int d = decltype(D)::value;
       const uint64_t v = acc[d] + carry;
@@ -297,7 +349,7 @@ __device__ __forceinline__ void hi_sb(const uint32_t (&a)[H], const uint32_t (&b
     constexpr int bk = (2 * H - 1 - w0) < BK ? (2 * H - 1 - w0) : BK;
     uint64_t acc[bk];
     sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
-    colblock<w0, bk, 0, H - 1, 0, H - 1>(a, b, acc);
+    colblock<w0, bk, 0, H - 1, 0, H - 1, false, PlainMad>(a, b, acc);
     sfor<0, bk>([&](auto D) {
       constexpr int d = decltype(D)::value;
       const uint64_t x = acc[d] + carry;

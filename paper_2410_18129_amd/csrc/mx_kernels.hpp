@@ -25,14 +25,17 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t v, uin
 }
 
 // Copies this lane's N and N' limbs into its LDS column ([limb][lane]).  Each
-// lane reads back only its own column, so no barrier is needed.
+// lane reads back only its own column, so no barrier is needed.  The reads of
+// each array are all issued before the first LDS write, so their latencies
+// overlap.
 template <int N>
 __device__ __forceinline__ void stage_ctx(uint32_t* s_ctx, const uint32_t* cn, const uint32_t* cnp, size_t cs,
                                           uint32_t lane) {
-  for (int i = 0; i < N; ++i) {
-    s_ctx[i * 64 + lane] = cn[(size_t)i * cs];
-    s_ctx[(N + i) * 64 + lane] = cnp[(size_t)i * cs];
-  }
+  uint32_t v[N];
+  sfor<0, N>([&](auto I) { v[decltype(I)::value] = cn[(size_t)decltype(I)::value * cs]; });
+  sfor<0, N>([&](auto I) { s_ctx[decltype(I)::value * 64 + lane] = v[decltype(I)::value]; });
+  sfor<0, N>([&](auto I) { v[decltype(I)::value] = cnp[(size_t)decltype(I)::value * cs]; });
+  sfor<0, N>([&](auto I) { s_ctx[(N + decltype(I)::value) * 64 + lane] = v[decltype(I)::value]; });
 }
 
 // ---- context: N, N' = -N^{-1} mod R, R mod N, R^2 mod N (Section 4) -------
@@ -126,16 +129,20 @@ __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restr
   uint32_t x[N];
   expand<N, RW>(a + (size_t)inst * RW, x);
   uint32_t t[2 * N];
+  // one product and one reduction per launch: the rotated carry-outs measure faster here
   if constexpr (SQR) {
-    sqr_sb<N>(x, t);
+    sqr_sb<N, RotMad>(x, t);
   } else {
     uint32_t y[N];
     expand<N, RW>(b + (size_t)inst * RW, y);
-    mul_sb<N>(x, y, t);
+    mul_sb<N, RotMad>(x, y, t);
   }
   uint32_t r[N];
-  const uint32_t* sm = s_ctx + threadIdx.x;
-  redc_blk<N, TRUNC>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, r);
+  // volatile reads: in this straight-line kernel the compiler would otherwise
+  // hoist every N and N' read to the staging point (the compiler barriers
+  // between column blocks do not order LDS reads) and spill them
+  const volatile uint32_t* sm = s_ctx + threadIdx.x;
+  redc_blk<N, TRUNC, RotMad>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, r);
   if (live) contract<N, RW>(r, out + (size_t)inst * RW);
 }
 
