@@ -205,10 +205,18 @@ def main():
     A = torch.nn.functional.pad(b2.base, (0, b2.ctx.mont_words - b2.ctx.words))
     B = torch.roll(A, 1, 0).contiguous()
     O = torch.empty_like(A)
-    for name, fn in (("modmul_per_s", lambda: mx.mont_mul(b2.ctx, A, B, out=O, stream=stream)),
-                     ("modsqr_per_s", lambda: mx.mont_sqr(b2.ctx, A, out=O, stream=stream))):
-        wl_, _ = time_launches(fn, 20, 3, stream)
-        res[name] = n * 20 / wl_
+    nl = counts.limbs(bits)
+    for op, fn in (("mul", lambda plain: mx.mont_mul(b2.ctx, A, B, out=O, plain=plain, stream=stream)),
+                   ("sqr", lambda plain: mx.mont_sqr(b2.ctx, A, out=O, plain=plain, stream=stream))):
+        rates = {}
+        for plain in (False, True):
+            wl_, kk = time_launches(lambda: fn(plain), 20, 3, stream)
+            rates[plain] = n * 20 / wl_
+            if not plain:
+                res["mod%s_per_s" % op] = rates[plain]
+                res["mod%s_frac" % op] = (counts.op_products(nl, True)[op] * n / (sum(kk) / len(kk) * 1e-3)
+                                          / counts.PEAK_MAD_PER_S)
+        res["mod%s_trunc_speedup" % op] = rates[False] / rates[True]
     b2.ctx.close()
     del b2
 

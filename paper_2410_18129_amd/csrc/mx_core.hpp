@@ -265,8 +265,11 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
   static_assert(N >= 3, "size class too small");
   constexpr int BK = kColBlock;
   uint32_t q[N];
-  // q = T_lo * N' mod R: columns 0 .. N-1, column k = sum_{i<=k} t[i] np[k-i]
-  uint64_t carry = 0;
+  // q = T_lo * N' mod R: columns 0 .. N-1, column k = sum_{i<=k} t[i] np[k-i].
+  // PLAIN: as soon as a block of q is known, the same columns of T + q N are
+  // formed too (they need q_0 .. q_k only); they vanish mod 2^28 and pass on
+  // their carry, and each limb of T_lo is dead once its column is done.
+  uint64_t carry = 0, lcarry = 0;
   sfor<0, (N + BK - 1) / BK>([&](auto B) {
     constexpr int k0 = decltype(B)::value * BK;
     constexpr int bk = (N - k0) < BK ? (N - k0) : BK;
@@ -279,12 +282,19 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
       q[k0 + d] = (uint32_t)v & kLimbMask;
       carry = v >> kLimbBits;
     });
+    if constexpr (!TRUNC) {
+      compiler_fence();
+      sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = t[k0 + decltype(D)::value]; });
+      colblock_ld<k0, bk, 0, N - 1, 0, N - 1, M>(q, ldm, acc);
+      sfor<0, bk>([&](auto D) { lcarry = (acc[decltype(D)::value] + lcarry) >> kLimbBits; });
+    }
     compiler_fence();
   });
-  // q * N: columns from n-2 (truncated, Theorem 2) or 0 (plain) to 2n-2
-  constexpr int W0 = TRUNC ? N - 2 : 0;
+  // q * N: columns from n-2 (truncated, Theorem 2) or n (plain, the low
+  // columns are done) to 2n-2
+  constexpr int W0 = TRUNC ? N - 2 : N;
   constexpr int NCOL = 2 * N - 1 - W0;
-  carry = 0;
+  carry = TRUNC ? 0 : lcarry;
   uint64_t a2 = 0;
   sfor<0, (NCOL + BK - 1) / BK>([&](auto B) {
     constexpr int w0 = W0 + decltype(B)::value * BK;
@@ -300,8 +310,6 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
       } else if constexpr (TRUNC && w == N - 1) {
         const uint64_t a1 = acc[d] + (a2 >> kLimbBits);
         carry = (a1 >> kLimbBits) + ((((uint32_t)a1 | (uint32_t)a2) & kLimbMask) != 0u ? 1u : 0u);
-      } else if constexpr (w < N) {
-        carry = (acc[d] + carry) >> kLimbBits;  // low limbs of T + qN vanish
       } else {
         const uint64_t v = acc[d] + carry;
         c[w - N] = (uint32_t)v & kLimbMask;
