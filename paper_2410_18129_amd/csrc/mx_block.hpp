@@ -68,14 +68,19 @@ __device__ __forceinline__ void zero_rows(const LaneBuf& b, uint32_t row, uint32
   for (uint32_t i = 0; i < len; ++i) b.st(row + i, 0u);
 }
 // Normalises len redundant limbs in place (chunks of C limbs held in
-// registers) and returns the carry out of the top limb.
+// registers) and returns the carry out of the top limb.  The next chunk is
+// read before the current one is processed, so the reads' latency overlaps.
 template <int C>
 __device__ __forceinline__ uint64_t norm_rows(const LaneBuf& b, uint32_t row, uint32_t len, uint64_t carry = 0) {
   uint32_t i = 0;
+  uint32_t x[C];
+  if (len >= C) ld_rows<C>(b, row, x);
 #pragma nounroll
   for (; i + C <= len; i += C) {
-    uint32_t x[C];
-    ld_rows<C>(b, row + i, x);
+    uint32_t nx[C];
+    const bool more = i + 2 * C <= len;
+    if (more) ld_rows<C>(b, row + i + C, nx);
+    compiler_fence();
     sfor<0, C>([&](auto I) {
       constexpr int k = decltype(I)::value;
       const uint64_t v = (uint64_t)x[k] + carry;
@@ -83,6 +88,7 @@ __device__ __forceinline__ uint64_t norm_rows(const LaneBuf& b, uint32_t row, ui
       carry = v >> kLimbBits;
     });
     st_rows<C>(b, row + i, x);
+    if (more) sfor<0, C>([&](auto I) { x[decltype(I)::value] = nx[decltype(I)::value]; });
   }
 #pragma nounroll
   for (; i < len; ++i) {
@@ -93,24 +99,28 @@ __device__ __forceinline__ uint64_t norm_rows(const LaneBuf& b, uint32_t row, ui
   return carry;
 }
 
-// rows[dst + i] = rows[src + i] for i < len, C limbs per register batch.
+// rows[dst + i] = rows[src + i] for i < len, C limbs per register batch, the
+// next batch read before the current one is written.
 template <int C>
 __device__ __forceinline__ void copy_rows(const LaneBuf& d, uint32_t dst, const LaneBuf& sb, uint32_t src,
                                           uint32_t len) {
   uint32_t i = 0;
+  uint32_t x[C];
+  if (len >= C) ld_rows<C>(sb, src, x);
 #pragma nounroll
   for (; i + C <= len; i += C) {
-    uint32_t x[C];
-    ld_rows<C>(sb, src + i, x);
+    uint32_t nx[C];
+    const bool more = i + 2 * C <= len;
+    if (more) ld_rows<C>(sb, src + i + C, nx);
+    compiler_fence();
     st_rows<C>(d, dst + i, x);
+    if (more) sfor<0, C>([&](auto I) { x[decltype(I)::value] = nx[decltype(I)::value]; });
   }
 #pragma nounroll
   for (; i < len; ++i) d.st(dst + i, sb.ld(src + i));
 }
 
-// One Montgomery product on the workspace: Y <- REDC(Y * B) or REDC(Y^2).
-// n = K H; context blocks come from the limb-major context arrays.
-// dst rows (dlen, zeroed here) += the product of the M-block numbers at rows
+// Karatsuba's half-size products: dst rows (dlen, zeroed here) += the product of the M-block numbers at rows
 // a and b (b ignored when sqr), as redundant limbs.  Within a row the next
 // operand block is loaded while the current block product runs, and the
 // accumulator rows are read before it, so memory latency overlaps the
@@ -258,101 +268,249 @@ __device__ __forceinline__ void kara_product(bool sqr, const LaneBuf& ws) {
   norm_rows_signed<H>(ws, Lay::T, 2 * n + 1);
 }
 
+// ---- block product scanning ---------------------------------------------
+//
+// The block products of one Montgomery operation are summed diagonal by
+// diagonal (block pairs (i, j) with i + j = c) into 64-bit column sums held
+// in registers, cols[L] for the global columns c H + L; when a diagonal is
+// done, its low H columns are final: they are normalised and written once,
+// and the high columns move down to start the next diagonal.  A column sum
+// is a partial sum of one column of the full product, at most
+// n (2^28 - 1)^2 < 2^64 for n <= 255 limbs, so it never overflows.  Each pair
+// loads its two operand blocks one pair ahead (the reads overlap the previous
+// pair's products); nothing is read back from the workspace.
+
+// cols[L] += sum over a[i] b[j] with i + j = L, CLO <= L <= CHI (and i > j when UPPER).
+template <int H, int CLO, int CHI, bool UPPER, int NC>
+__device__ __forceinline__ void blk_cols(uint64_t (&cols)[NC], const uint32_t (&a)[H], const uint32_t (&b)[H]) {
+  constexpr int BK = kColBlock;
+  sfor<0, (CHI - CLO + BK) / BK>([&](auto Bc) {
+    constexpr int k0 = CLO + decltype(Bc)::value * BK;
+    constexpr int bk = (CHI + 1 - k0) < BK ? (CHI + 1 - k0) : BK;
+    colblock<k0, bk, 0, H - 1, 0, H - 1, UPPER, PlainMad>(a, b, *reinterpret_cast<uint64_t(*)[bk]>(&cols[k0]));
+  });
+}
+
+// Normalises cols[0 .. H-1] with the running carry into o, then moves the
+// high columns down by H (the next diagonal's window).
+template <int H>
+__device__ __forceinline__ void blk_emit(uint64_t (&cols)[2 * H], uint64_t& carry, uint32_t (&o)[H]) {
+  sfor<0, H>([&](auto D) {
+    constexpr int d = decltype(D)::value;
+    const uint64_t v = cols[d] + carry;
+    o[d] = (uint32_t)v & kLimbMask;
+    carry = v >> kLimbBits;
+  });
+  sfor<0, H>([&](auto D) {
+    constexpr int d = decltype(D)::value;
+    cols[d] = cols[d + H];
+    cols[d + H] = 0;
+  });
+}
+
+// T = Y * B or Y^2 (Section 2 at block level; squares: pairs i <= j, the
+// cross pairs with a doubled operand, the diagonal blocks as Algorithm 2).
+// T rows: 2n normalised limbs and a zero top row.
+template <int H, int K>
+__device__ __forceinline__ void scan_product(bool sqr, const LaneBuf& ws) {
+  using Lay = BlkLayout<H, K>;
+  const uint32_t rb = sqr ? Lay::Y : Lay::B;
+  uint64_t cols[2 * H];
+  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  uint64_t carry = 0;
+  uint32_t a[H], b[H];
+  ld_rows<H>(ws, Lay::Y, a);
+  ld_rows<H>(ws, rb, b);
+  uint32_t c = 0, i = 0;
+#pragma nounroll
+  for (;;) {
+    const uint32_t j = c - i;
+    uint32_t nc = c, ni = i + 1;
+    if (ni > (c < K ? c : K - 1) || (sqr && ni > c - ni)) {
+      nc = c + 1;
+      ni = nc >= K ? nc - K + 1 : 0u;
+    }
+    const bool more = nc < 2 * K - 1;
+    uint32_t na[H], nb[H];
+    if (more) {
+      ld_rows<H>(ws, Lay::Y + ni * H, na);
+      ld_rows<H>(ws, rb + (nc - ni) * H, nb);
+    }
+    compiler_fence();
+    if (sqr && i == j) {
+      uint32_t a2[H];
+      sfor<0, H>([&](auto P) { a2[decltype(P)::value] = a[decltype(P)::value] << 1; });
+      blk_cols<H, 0, 2 * H - 2, true>(cols, a, a2);
+      sfor<0, H>([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        cols[2 * p] += (uint64_t)a[p] * a[p];
+      });
+    } else {
+      if (sqr) sfor<0, H>([&](auto P) { b[decltype(P)::value] <<= 1; });
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+    }
+    if (nc != c) {  // diagonal c done: block c of T is final
+      uint32_t o[H];
+      blk_emit<H>(cols, carry, o);
+      st_rows<H>(ws, Lay::T + c * H, o);
+    }
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    i = ni;
+    sfor<0, H>([&](auto P) {
+      a[decltype(P)::value] = na[decltype(P)::value];
+      b[decltype(P)::value] = nb[decltype(P)::value];
+    });
+  }
+  uint32_t o[H];
+  blk_emit<H>(cols, carry, o);
+  st_rows<H>(ws, Lay::T + (2 * K - 1) * H, o);
+  ws.st(Lay::T + 2 * Lay::n, (uint32_t)carry);
+}
+
+// q = T_lo * N' mod R (Algorithm 6 step 1): diagonals 0 .. K-1, the last one
+// low halves only; q blocks to the Q rows.
+template <int H, int K>
+__device__ __forceinline__ void scan_q(const LaneBuf& ws, const LaneBuf& cnp) {
+  using Lay = BlkLayout<H, K>;
+  uint64_t cols[2 * H];
+  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  uint64_t carry = 0;
+  uint32_t a[H], b[H];
+  ld_rows<H>(ws, Lay::T, a);
+  ld_rows<H>(cnp, 0, b);
+  uint32_t c = 0, i = 0;
+#pragma nounroll
+  for (;;) {
+    uint32_t nc = c, ni = i + 1;
+    if (ni > c) {
+      nc = c + 1;
+      ni = 0;
+    }
+    const bool more = nc < K;
+    uint32_t na[H], nb[H];
+    if (more) {
+      ld_rows<H>(ws, Lay::T + ni * H, na);
+      ld_rows<H>(cnp, (nc - ni) * H, nb);
+    }
+    compiler_fence();
+    if (c + 1 < K)
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+    else
+      blk_cols<H, 0, H - 1, false>(cols, a, b);
+    if (nc != c) {
+      uint32_t o[H];
+      blk_emit<H>(cols, carry, o);  // the carry out of block K-1 is dropped: mod R
+      st_rows<H>(ws, Lay::Q + c * H, o);
+    }
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    i = ni;
+    sfor<0, H>([&](auto P) {
+      a[decltype(P)::value] = na[decltype(P)::value];
+      b[decltype(P)::value] = nb[decltype(P)::value];
+    });
+  }
+}
+
+// Y = (T + q N) / R (Algorithm 6 step 4 / Algorithm 3).  TRUNC (Theorem 2):
+// diagonals from K-1, whose block pairs contribute only their columns
+// >= H-2 (global columns >= n-2), plus the top partial product of each pair
+// on diagonal K-2 (global column n-2); the exact sums a2, a1 of columns n-2
+// and n-1 give the carry into column n with the ceil correction for the
+// skipped columns.  PLAIN: every diagonal; the low columns vanish and pass on
+// their carry.
+template <int H, int K, bool TRUNC>
+__device__ __forceinline__ void scan_qn(const LaneBuf& ws, const LaneBuf& cn) {
+  using Lay = BlkLayout<H, K>;
+  uint64_t cols[2 * H];
+  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  uint64_t carry = 0;
+  constexpr uint32_t c0 = TRUNC ? K - 1 : 0;
+  if constexpr (TRUNC && K >= 2) {
+#pragma nounroll
+    for (uint32_t i = 0; i + 2 <= K; ++i)
+      cols[H - 2] += (uint64_t)ws.ld(Lay::Q + i * H + H - 1) * cn.ld((K - 2 - i) * H + H - 1);
+  }
+  uint32_t a[H], b[H];
+  {
+    const uint32_t i0 = c0 >= K ? c0 - K + 1 : 0u;
+    ld_rows<H>(ws, Lay::Q + i0 * H, a);
+    ld_rows<H>(cn, (c0 - i0) * H, b);
+  }
+  uint32_t c = c0, i = c0 >= K ? c0 - K + 1 : 0u;
+#pragma nounroll
+  for (;;) {
+    uint32_t nc = c, ni = i + 1;
+    if (ni > (c < K ? c : K - 1)) {
+      nc = c + 1;
+      ni = nc >= K ? nc - K + 1 : 0u;
+    }
+    const bool more = nc < 2 * K - 1;
+    uint32_t na[H], nb[H];
+    if (more) {
+      ld_rows<H>(ws, Lay::Q + ni * H, na);
+      ld_rows<H>(cn, (nc - ni) * H, nb);
+    }
+    compiler_fence();
+    if (TRUNC && c == K - 1)
+      blk_cols<H, H - 2, 2 * H - 2, false>(cols, a, b);
+    else
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+    if (nc != c) {  // diagonal c done: add block c of T, then emit or fold the carry
+      uint32_t tb[H];
+      ld_rows<H>(ws, Lay::T + c * H, tb);
+      sfor<0, H>([&](auto D) { cols[decltype(D)::value] += tb[decltype(D)::value]; });
+      uint32_t o[H];
+      if (TRUNC && c == K - 1) {
+        const uint64_t a2 = cols[H - 2];
+        const uint64_t a1 = cols[H - 1] + (a2 >> kLimbBits);
+        carry = (a1 >> kLimbBits) + ((((uint32_t)a1 | (uint32_t)a2) & kLimbMask) != 0u ? 1u : 0u);
+        sfor<0, H>([&](auto D) {
+          constexpr int d = decltype(D)::value;
+          cols[d] = cols[d + H];
+          cols[d + H] = 0;
+        });
+      } else if (c < K) {  // PLAIN, low columns: they vanish mod 2^28
+        blk_emit<H>(cols, carry, o);
+      } else {
+        blk_emit<H>(cols, carry, o);
+        st_rows<H>(ws, Lay::Y + (c - K) * H, o);
+      }
+    }
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    i = ni;
+    sfor<0, H>([&](auto P) {
+      a[decltype(P)::value] = na[decltype(P)::value];
+      b[decltype(P)::value] = nb[decltype(P)::value];
+    });
+  }
+  // the top block: columns (2K-1) H .. 2n-1 and T's top limbs
+  uint32_t tb[H];
+  ld_rows<H>(ws, Lay::T + (2 * K - 1) * H, tb);
+  sfor<0, H>([&](auto D) { cols[decltype(D)::value] += tb[decltype(D)::value]; });
+  uint32_t o[H];
+  blk_emit<H>(cols, carry, o);  // C < 2N < R: no carry remains
+  st_rows<H>(ws, Lay::Y + (K - 1) * H, o);
+}
+
+// One Montgomery product on the workspace: Y <- REDC(Y * B) or REDC(Y^2).
+// n = K H; context blocks come from the limb-major context arrays.
 template <int H, int K, bool TRUNC, bool KARA = false>
 __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const LaneBuf& cn, const LaneBuf& cnp) {
-  using Lay = BlkLayout<H, K>;
-  constexpr uint32_t n = Lay::n;
   // ---- product T = Y * B (or Y^2): Section 2 at block level, or Section 3 --
-  if constexpr (KARA) {
+  if constexpr (KARA)
     kara_product<H, K>(sqr, ws);
-  } else {
-    blk_product<H>(sqr, ws, Lay::Y, sqr ? Lay::Y : Lay::B, K, Lay::T, 2 * n + 1);
-    norm_rows<H>(ws, Lay::T, 2 * n + 1);
-  }
+  else
+    scan_product<H, K>(sqr, ws);
   // ---- q = T_lo * N' mod R: pairs i + j <= K - 1 (Algorithm 6 step 1) ------
-  zero_rows(ws, Lay::Q, n);
-#pragma nounroll
-  for (uint32_t i = 0; i < K; ++i) {
-    uint32_t a[H], b[H];
-    ld_rows<H>(ws, Lay::T + i * H, a);
-    ld_rows<H>(cnp, 0, b);
-#pragma nounroll
-    for (uint32_t j = 0; i + j < K; ++j) {
-      uint32_t acc[2 * H], bn[H];
-      const bool full = i + j + 1 < K;
-      if (full)
-        ld_rows<2 * H>(ws, Lay::Q + (i + j) * H, acc);
-      else
-        ld_rows<H>(ws, Lay::Q + (i + j) * H, *reinterpret_cast<uint32_t(*)[H]>(acc));
-      if (i + j + 1 < K) ld_rows<H>(cnp, (j + 1) * H, bn);
-      compiler_fence();
-      if (full) {
-        uint32_t t[2 * H];
-        mul_sb<H>(a, b, t);
-        sfor<0, 2 * H>([&](auto I) { acc[decltype(I)::value] += t[decltype(I)::value]; });
-        st_rows<2 * H>(ws, Lay::Q + (i + j) * H, acc);
-      } else {
-        uint32_t l[H];
-        lo_sb<H>(a, b, l);
-        sfor<0, H>([&](auto I) { acc[decltype(I)::value] += l[decltype(I)::value]; });
-        st_rows<H>(ws, Lay::Q + (i + j) * H, *reinterpret_cast<uint32_t(*)[H]>(acc));
-      }
-      compiler_fence();
-      if (i + j + 1 < K) sfor<0, H>([&](auto I) { b[decltype(I)::value] = bn[decltype(I)::value]; });
-    }
-  }
-  (void)norm_rows<H>(ws, Lay::Q, n);  // the carry out of limb n - 1 is dropped: mod R
-  // ---- S = T + q N over the needed columns ---------------------------------
-  // TRUNC: S holds columns n-2 .. 2n (row S + c is column n - 2 + c).
-  // PLAIN: S holds columns 0 .. 2n (row S + c is column c).
-  constexpr uint32_t c0 = TRUNC ? n - 2 : 0;
-  constexpr uint32_t slen = 2 * n + 1 - c0;
-  copy_rows<H>(ws, Lay::S, ws, Lay::T + c0, slen);
-#pragma nounroll
-  for (uint32_t i = 0; i < K; ++i) {
-    uint32_t a[H], b[H];
-    ld_rows<H>(ws, Lay::Q + i * H, a);
-    const uint32_t j0 = (TRUNC && i + 2 < K) ? K - 2 - i : 0u;
-    ld_rows<H>(cn, j0 * H, b);
-#pragma nounroll
-    for (uint32_t j = j0; j < K; ++j) {
-      uint32_t bn[H];
-      if (j + 1 < K) ld_rows<H>(cn, (j + 1) * H, bn);
-      if (!TRUNC || i + j >= K) {
-        uint32_t acc[2 * H];
-        ld_rows<2 * H>(ws, Lay::S + (i + j) * H - c0, acc);
-        compiler_fence();
-        uint32_t t[2 * H];
-        mul_sb<H>(a, b, t);
-        sfor<0, 2 * H>([&](auto I) { acc[decltype(I)::value] += t[decltype(I)::value]; });
-        st_rows<2 * H>(ws, Lay::S + (i + j) * H - c0, acc);
-      } else if (i + j + 1 == K) {
-        uint32_t acc[H + 2];
-        ld_rows<H + 2>(ws, Lay::S, acc);
-        compiler_fence();
-        uint32_t v[H + 2];
-        hi_sb<H>(a, b, v);
-        sfor<0, H + 2>([&](auto I) { acc[decltype(I)::value] += v[decltype(I)::value]; });
-        st_rows<H + 2>(ws, Lay::S, acc);
-      } else {  // i + j == K - 2: its top partial product sits at column n - 2
-        const uint64_t p = (uint64_t)a[H - 1] * b[H - 1];
-        uint32_t v[2] = {(uint32_t)p & kLimbMask, (uint32_t)(p >> kLimbBits)};
-        add_rows<2>(ws, Lay::S, v, 1u);
-      }
-      compiler_fence();
-      if (j + 1 < K) sfor<0, H>([&](auto I) { b[decltype(I)::value] = bn[decltype(I)::value]; });
-    }
-  }
-  if constexpr (TRUNC) {
-    // exact value of columns >= n-2, then the ceil correction for the skipped columns
-    (void)norm_rows<H>(ws, Lay::S, slen);
-    const uint32_t lowz = (ws.ld(Lay::S) | ws.ld(Lay::S + 1)) != 0u ? 1u : 0u;
-    (void)norm_rows<H>(ws, Lay::S + 2, n, lowz);  // adds the correction, result < 2N < R
-    copy_rows<H>(ws, Lay::Y, ws, Lay::S + 2, n);
-  } else {
-    (void)norm_rows<H>(ws, Lay::S, slen);  // limbs 0 .. n-1 are zero: T + qN = 0 mod R
-    copy_rows<H>(ws, Lay::Y, ws, Lay::S + n, n);
-  }
+  scan_q<H, K>(ws, cnp);
+  // ---- C = (T + q N) / R, truncated (Theorem 2) or whole (Algorithm 3) -----
+  scan_qn<H, K, TRUNC>(ws, cn);
 }
 
 // Loads the RW-word little-endian value at src into rows row .. row+n-1 (28-bit limbs).
