@@ -683,6 +683,7 @@ __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* _
   const uint32_t tile0 = blockIdx.x * 64;
   const uint32_t tbytes = BlkLayout<H, K>::rows(w) * 256u;  // this block's region
   if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  stagger<H * K>(blockIdx.x, w);
   modexp_tile_blk<H, K, TRUNC, KARA>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
                                      ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0);
 }

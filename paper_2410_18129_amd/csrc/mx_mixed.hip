@@ -57,6 +57,9 @@ __global__ void k_reset_counter(uint32_t* counter) {
 __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
   __shared__ uint32_t s_ctx[2 * 74 * 64];  // N, N' staging of the largest register-resident class
   const uint32_t lane = threadIdx.x & 63u;
+  // the first tiles of all waves start together and are the costliest (the
+  // largest class): spread their start phases as a 4096-bit, window-5 launch does
+  stagger<148>(blockIdx.x, 5u);
   for (;;) {
     uint32_t j = 0;
     if (lane == 0) j = atomicAdd(args.counter, 1u);
