@@ -631,21 +631,30 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
       if (width > 0 && sh + width > 64 && lo + 1 < ewords) v |= e64[lo + 1] << (64 - sh);
       const uint32_t bits = (uint32_t)v & ((1u << width) - 1u);
       const uint32_t dst = kind == kLoadSel ? Lay::Y : Lay::B;
-      // full masked scan of the table, H limbs at a time
+      // full masked scan of the table, H limbs at a time, SE entries per
+      // iteration (SE H reads in flight; the registers of the Montgomery
+      // operation are free here).  With fewer than SE entries (w < 3) the
+      // missing ones re-read entry 0 under a zero mask.
+      constexpr uint32_t SE = 8;
 #pragma nounroll
       for (uint32_t blk = 0; blk < K; ++blk) {
         uint32_t acc[H];
         sfor<0, H>([&](auto I) { acc[decltype(I)::value] = 0; });
 #pragma nounroll
-        for (uint32_t e = 0; e < nent; e += 2) {
-          const uint32_t mask0 = e == bits ? 0xFFFFFFFFu : 0u;
-          const uint32_t mask1 = e + 1 == bits ? 0xFFFFFFFFu : 0u;
-          uint32_t g0[H], g1[H];
-          ld_rows<H>(ws, Lay::G + e * n + blk * H, g0);
-          ld_rows<H>(ws, Lay::G + (e + 1) * n + blk * H, g1);
+        for (uint32_t e = 0; e < nent; e += SE) {
+          uint32_t g[SE][H];
+          uint32_t mask[SE];
+          sfor<0, SE>([&](auto U) {
+            constexpr uint32_t u = decltype(U)::value;
+            const bool in = e + u < nent;
+            mask[u] = in && e + u == bits ? 0xFFFFFFFFu : 0u;
+            ld_rows<H>(ws, Lay::G + (in ? e + u : 0u) * n + blk * H, g[u]);
+          });
           sfor<0, H>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            acc[i] |= (g0[i] & mask0) | (g1[i] & mask1);
+            uint32_t v = acc[i];
+            sfor<0, SE>([&](auto U) { v |= g[decltype(U)::value][i] & mask[decltype(U)::value]; });
+            acc[i] = v;
           });
         }
         st_rows<H>(ws, dst + blk * H, acc);

@@ -44,6 +44,24 @@ def test_block_kernels_match_register_kernels(mx, bits):
     ctx.close()
 
 
+@pytest.mark.parametrize("window", [1, 2, 3, 8])
+def test_block_kernel_small_and_large_windows(mx, window):
+    # the block kernels' table scan reads eight entries per iteration: windows 1 and 2
+    # (fewer than eight entries) re-read entry 0 under a zero mask; window 8 is the largest
+    bits, n = 1024, 67
+    mods = wl.random_moduli(wl.stream(12, "moduli"), bits, n)
+    ctx = mx.Context(mods, bits)
+    base = wl.random_below_fast(wl.stream(12, "bases"), mods, bits)
+    exps = wl.random_exponents(wl.stream(12, "exps"), bits, n)
+    bd, ed = mx.to_device(base), mx.to_device(exps)
+    r_blk = dev_ints(mx.modexp(ctx, bd, ed, bits, window=window, block=True))
+    assert r_blk == dev_ints(mx.modexp(ctx, bd, ed, bits, window=window))
+    M, Bs, Es = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
+    for i in (0, 33, n - 1):
+        assert r_blk[i] == oracle.modexp(Bs[i], Es[i], M[i], bits)
+    ctx.close()
+
+
 def test_block_flag_unsupported_class(mx):
     ctx = mx.Context(wl.random_moduli(wl.stream(12, "moduli"), 256, 1), 256)
     a = ints_dev([1], ctx.mont_words)
