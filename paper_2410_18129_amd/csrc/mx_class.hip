@@ -34,7 +34,7 @@ hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
 uint32_t ws_rows_fn(int impl, bool modexp, uint32_t w) {
   if (kBlock || (kHasBlk && impl >= 1)) return modexp ? BlkLayout<kH, kK>::rows(w) : BlkLayout<kH, kK>::G;
   (void)impl;
-  return modexp ? (1u << w) * (uint32_t)kN : 0u;
+  return modexp ? (1u << w) * (uint32_t)packed_words(kN) : 0u;  // densely packed table entries
 }
 
 hipError_t mont_fn(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,

@@ -406,6 +406,43 @@ __device__ __forceinline__ void contract(const uint32_t (&x)[N], uint64_t* __res
   });
 }
 
+// ---- dense packing of 28-bit limbs into 32-bit words (window table) --------
+
+// Words holding N 28-bit limbs.
+constexpr int packed_words(int n) { return (kLimbBits * n + 31) / 32; }
+
+// w = the N limbs of x as a dense little-endian bit string of packed_words(N) words.
+template <int N>
+__device__ __forceinline__ void pack(const uint32_t (&x)[N], uint32_t (&w)[packed_words(N)]) {
+  sfor<0, packed_words(N)>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    uint32_t v = 0;
+    sfor<0, N>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int lo = kLimbBits * i - 32 * j;  // bit position of limb i inside word j
+      if constexpr (lo > -kLimbBits && lo < 32) {
+        if constexpr (lo >= 0)
+          v |= x[i] << lo;
+        else
+          v |= x[i] >> (-lo);
+      }
+    });
+    w[j] = v;
+  });
+}
+
+// x = the N 28-bit limbs of the dense bit string w.
+template <int N>
+__device__ __forceinline__ void unpack(const uint32_t (&w)[packed_words(N)], uint32_t (&x)[N]) {
+  sfor<0, N>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int bit = kLimbBits * i, wd = bit / 32, off = bit % 32;
+    uint32_t v = w[wd] >> off;
+    if constexpr (off > 32 - kLimbBits && wd + 1 < packed_words(N)) v |= w[wd + 1] << (32 - off);
+    x[i] = v & kLimbMask;
+  });
+}
+
 // c = x - m if x >= m else x (constant time; x <= m on entry gives [0, m)).
 template <int N>
 __device__ __forceinline__ void canon(uint32_t (&x)[N], const uint32_t (&m)[N]) {

@@ -184,10 +184,11 @@ __device__ __forceinline__ void stagger(uint32_t block, uint32_t w) {
 // Modular exponentiation of one tile of 64 instances (one wavefront).
 // tile0: first instance of the tile; lane l handles instance tile0 + l (the
 // lanes past `count` recompute the last instance and store nothing).
-// table: this wavefront's own workspace region of tbytes >= 2^w N 256 bytes,
-// limb-major over its 64 lanes (entry e, limb i of lane l at byte
-// (e N + i) 256 + 4 l), so that every read of the table scan is a whole
-// 256-byte row and a wavefront's table is one contiguous range of memory.
+// table: this wavefront's own workspace region of tbytes >= 2^w NW 256 bytes,
+// word-major over its 64 lanes (entry e, word j of lane l at byte
+// (e NW + j) 256 + 4 l, NW = packed_words(N): the entry's limbs packed
+// densely), so that every read of the table scan is a whole 256-byte row and
+// a wavefront's table is one contiguous range of memory.
 // s_ctx: 2 N 64 words of LDS for the lane's N and N'.
 template <int N, int BW, bool TRUNC>
 __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
@@ -206,7 +207,10 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
   const size_t cs = ctx.stride;
   const __amdgpu_buffer_rsrc_t tr = make_buf(table, tbytes);
   const uint32_t tvo = lane * 4u;
-  const uint32_t tls = 256u;  // bytes between consecutive limbs
+  const uint32_t tls = 256u;  // bytes between consecutive words of an entry
+  // entries are stored densely packed: NW 32-bit words of 28-bit limbs
+  constexpr int NW = packed_words(N);
+  const uint32_t ent_bytes = (uint32_t)NW * tls;
   const uint64_t* e64 = ex + (size_t)inst * ewords;
 
   const uint32_t nent = 1u << w;
@@ -215,10 +219,13 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
   stage_ctx<N>(s_ctx, cn, cnp, cs, lane);
   const uint32_t* sm = s_ctx + lane;
 
-  // G[0] = R mod N
-  for (int i = 0; i < N; ++i) bstore(tr, ctx.r1[(size_t)i * cs + c], tvo, (uint32_t)i * tls);
-
   uint32_t y[N];
+  {  // G[0] = R mod N
+    sfor<0, N>([&](auto I) { y[decltype(I)::value] = ctx.r1[(size_t)decltype(I)::value * cs + c]; });
+    uint32_t pw[NW];
+    pack<N>(y, pw);
+    sfor<0, NW>([&](auto J) { bstore(tr, pw[decltype(J)::value], tvo, (uint32_t)decltype(J)::value * tls); });
+  }
   expand<N, BW>(base + (size_t)inst * BW, y);
 
   const uint32_t n_tab = nent - 1;              // REDC(base R^2), then nent - 2 table products
@@ -254,24 +261,26 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
       if (width > 0 && sh + width > 64 && lo + 1 < ewords) v |= e64[lo + 1] << (64 - sh);
       const uint32_t bits = (uint32_t)v & ((1u << width) - 1u);
       // full masked scan: every entry is read, the selected one survives
-      sfor<0, N>([&](auto I) { bsrc[decltype(I)::value] = 0; });
-      // two entries per iteration keep 2N loads in flight (nent >= 2)
+      uint32_t selw[NW];
+      sfor<0, NW>([&](auto I) { selw[decltype(I)::value] = 0; });
+      // two entries per iteration keep 2 NW loads in flight (nent >= 2)
 #pragma nounroll
       for (uint32_t e = 0; e < nent; e += 2) {
         const uint32_t mask0 = e == bits ? 0xFFFFFFFFu : 0u;
         const uint32_t mask1 = e + 1 == bits ? 0xFFFFFFFFu : 0u;
-        const uint32_t s0 = e * (uint32_t)N * tls;
-        uint32_t v0[N], v1[N];
-        sfor<0, N>([&](auto I) {
+        const uint32_t s0 = e * ent_bytes;
+        uint32_t v0[NW], v1[NW];
+        sfor<0, NW>([&](auto I) {
           constexpr int i = decltype(I)::value;
           v0[i] = bload(tr, tvo, s0 + (uint32_t)i * tls);
-          v1[i] = bload(tr, tvo, s0 + (uint32_t)(N + i) * tls);
+          v1[i] = bload(tr, tvo, s0 + ent_bytes + (uint32_t)i * tls);
         });
-        sfor<0, N>([&](auto I) {
+        sfor<0, NW>([&](auto I) {
           constexpr int i = decltype(I)::value;
-          bsrc[i] |= (v0[i] & mask0) | (v1[i] & mask1);
+          selw[i] |= (v0[i] & mask0) | (v1[i] & mask1);
         });
       }
+      unpack<N>(selw, bsrc);
       if (kind == kLoadSel) {
         sfor<0, N>([&](auto I) { y[decltype(I)::value] = bsrc[decltype(I)::value]; });
         continue;
@@ -284,10 +293,9 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
           bsrc[i] = src[(size_t)i * cs];
         });
       } else {
-        sfor<0, N>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          bsrc[i] = bload(tr, tvo, (uint32_t)(N + i) * tls);
-        });
+        uint32_t pw[NW];
+        sfor<0, NW>([&](auto I) { pw[decltype(I)::value] = bload(tr, tvo, ent_bytes + (uint32_t)decltype(I)::value * tls); });
+        unpack<N>(pw, bsrc);
       }
     } else if (kind == kMulOne) {
       sfor<0, N>([&](auto I) { bsrc[decltype(I)::value] = decltype(I)::value == 0 ? 1u : 0u; });
@@ -300,11 +308,10 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
       mul_sb<N>(y, bsrc, t);
     redc_blk<N, TRUNC>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, y);
     if (store_e >= 0) {
-      const uint32_t s0 = (uint32_t)store_e * (uint32_t)N * tls;
-      sfor<0, N>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        bstore(tr, y[i], tvo, s0 + (uint32_t)i * tls);
-      });
+      const uint32_t s0 = (uint32_t)store_e * ent_bytes;
+      uint32_t pw[NW];
+      pack<N>(y, pw);
+      sfor<0, NW>([&](auto I) { bstore(tr, pw[decltype(I)::value], tvo, s0 + (uint32_t)decltype(I)::value * tls); });
     }
   }
   uint32_t m[N];
@@ -313,7 +320,7 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
   if (live) contract<N, BW>(y, out + (size_t)inst * BW);
 }
 
-// ws: ceil(count / 64) tile regions of 2^w N 256 bytes each, one per block.
+// ws: ceil(count / 64) tile regions of 2^w packed_words(N) 256 bytes each, one per block.
 template <int N, int BW, bool TRUNC>
 __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
@@ -322,7 +329,7 @@ __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __res
                                                uint32_t ws_bytes, uint32_t coff) {
   __shared__ uint32_t s_ctx[2 * N * 64];
   const uint32_t tile0 = blockIdx.x * 64;
-  const uint32_t tbytes = (1u << w) * (uint32_t)N * 256u;
+  const uint32_t tbytes = (1u << w) * (uint32_t)packed_words(N) * 256u;
   if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
   stagger<N>(blockIdx.x, w);
   modexp_tile<N, BW, TRUNC>(ctx, cidx, base, ex, ebits, ewords, w, out, count, ws + (size_t)blockIdx.x * (tbytes / 4u),
