@@ -140,8 +140,9 @@ def main():
         copy_probe()
         return
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); instances are independent, "
-              "DESIGN.md section 9 describes how the batch would shard" % a.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus %d requested); the instances are independent, so a "
+              "multi-GPU run would shard the batch by instance with no exchange on the hot path" % a.gpus,
+              file=sys.stderr)
         sys.exit(2)
     if not a.quick:
         # the serving workload runs 4 x SERVE_SLOTS streams concurrently: give each its own hardware
