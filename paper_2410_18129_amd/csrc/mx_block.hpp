@@ -498,19 +498,270 @@ __device__ __forceinline__ void scan_qn(const LaneBuf& ws, const LaneBuf& cn) {
   st_rows<H>(ws, Lay::Y + (K - 1) * H, o);
 }
 
+// ---- two lanes per instance ------------------------------------------------
+//
+// For batches too small to give every SIMD a wavefront, lanes 2m and 2m+1
+// hold the same instance and halve its latency.  The block pairs of each
+// diagonal are dealt to the two lanes alternately (a lane left without a
+// pair in a diagonal's last slot multiplies by zero); each lane accumulates
+// its own partial column sums, and when a diagonal's low columns are emitted
+// the two partial sums are added across the lane pair (a DPP swap of
+// adjacent lanes), so both lanes normalise the same totals and write the
+// same limbs.  Square blocks are formed as whole block products here (the
+// partner lane may be running a cross pair in the same instructions).
+
+// v + the same variable of the partner lane (lanes 2m, 2m+1)
+__device__ __forceinline__ uint64_t pair_sum(uint64_t v) {
+  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+  return v + (((uint64_t)phi << 32) | plo);
+}
+
+// blk_emit on the pair's summed columns
+template <int H>
+__device__ __forceinline__ void blk_emit2(uint64_t (&cols)[2 * H], uint64_t& carry, uint32_t (&o)[H]) {
+  sfor<0, H>([&](auto D) {
+    constexpr int d = decltype(D)::value;
+    const uint64_t v = pair_sum(cols[d]) + carry;
+    o[d] = (uint32_t)v & kLimbMask;
+    carry = v >> kLimbBits;
+  });
+  sfor<0, H>([&](auto D) {
+    constexpr int d = decltype(D)::value;
+    cols[d] = cols[d + H];
+    cols[d + H] = 0;
+  });
+}
+
+// This lane's view of block `blk` of an array: row r of the result is row
+// blk H + r of the array.
+__device__ __forceinline__ LaneBuf blk_view(const LaneBuf& b, uint32_t blk, uint32_t h) {
+  return LaneBuf{b.r, b.vo + blk * h * b.ls, b.ls};
+}
+
+// Pairs (i, c - i) of diagonal c, i >= ilo: their count, for the product
+// (squares: i <= c - i), the q triangle (c < K) and q N.
+template <int K>
+__device__ __forceinline__ uint32_t diag_ilo(uint32_t c) { return c >= K ? c - K + 1 : 0u; }
+template <int K>
+__device__ __forceinline__ uint32_t diag_pairs(uint32_t c, bool sqr) {
+  const uint32_t ilo = diag_ilo<K>(c), ihi = c < K ? c : K - 1;
+  const uint32_t top = sqr && c / 2 < ihi ? c / 2 : ihi;
+  return top - ilo + 1;
+}
+
+template <int H, int K>
+__device__ __forceinline__ void scan2_product(bool sqr, const LaneBuf& ws) {
+  using Lay = BlkLayout<H, K>;
+  const uint32_t rb = sqr ? Lay::Y : Lay::B;
+  const uint32_t r = threadIdx.x & 1u;
+  uint64_t cols[2 * H];
+  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  uint64_t carry = 0;
+  // slot s of diagonal c: this lane's pair is i = ilo + 2 s + r, if it exists
+  auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[H], uint32_t& sh, bool& valid) {
+    const uint32_t k = 2 * s + r;
+    valid = k < diag_pairs<K>(c, sqr);
+    const uint32_t i = diag_ilo<K>(c) + (valid ? k : 0u), j = c - i;
+    ld_rows<H>(blk_view(ws, i, H), Lay::Y, x);
+    ld_rows<H>(blk_view(ws, j, H), rb, y);
+    sh = sqr && i < j ? 1u : 0u;  // cross pairs of a square count twice
+  };
+  uint32_t a[H], b[H], sh;
+  bool valid;
+  load(0, 0, a, b, sh, valid);
+  uint32_t c = 0, s = 0;
+#pragma nounroll
+  for (;;) {
+    uint32_t nc = c, ns = s + 1;
+    if (2 * ns >= diag_pairs<K>(c, sqr)) {
+      nc = c + 1;
+      ns = 0;
+    }
+    const bool more = nc < 2 * K - 1;
+    uint32_t na[H], nb[H], nsh = 0;
+    bool nvalid = false;
+    if (more) load(nc, ns, na, nb, nsh, nvalid);
+    compiler_fence();
+    sfor<0, H>([&](auto P) { b[decltype(P)::value] = valid ? b[decltype(P)::value] << sh : 0u; });
+    blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+    if (nc != c) {
+      uint32_t o[H];
+      blk_emit2<H>(cols, carry, o);
+      st_rows<H>(ws, Lay::T + c * H, o);
+    }
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    s = ns;
+    sh = nsh;
+    valid = nvalid;
+    sfor<0, H>([&](auto P) {
+      a[decltype(P)::value] = na[decltype(P)::value];
+      b[decltype(P)::value] = nb[decltype(P)::value];
+    });
+  }
+  uint32_t o[H];
+  blk_emit2<H>(cols, carry, o);
+  st_rows<H>(ws, Lay::T + (2 * K - 1) * H, o);
+  ws.st(Lay::T + 2 * Lay::n, (uint32_t)carry);
+}
+
+template <int H, int K>
+__device__ __forceinline__ void scan2_q(const LaneBuf& ws, const LaneBuf& cnp) {
+  using Lay = BlkLayout<H, K>;
+  const uint32_t r = threadIdx.x & 1u;
+  uint64_t cols[2 * H];
+  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  uint64_t carry = 0;
+  auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[H], bool& valid) {
+    const uint32_t k = 2 * s + r;
+    valid = k <= c;
+    const uint32_t i = valid ? k : 0u;
+    ld_rows<H>(blk_view(ws, i, H), Lay::T, x);
+    ld_rows<H>(blk_view(cnp, c - i, H), 0, y);
+  };
+  uint32_t a[H], b[H];
+  bool valid;
+  load(0, 0, a, b, valid);
+  uint32_t c = 0, s = 0;
+#pragma nounroll
+  for (;;) {
+    uint32_t nc = c, ns = s + 1;
+    if (2 * ns > c) {
+      nc = c + 1;
+      ns = 0;
+    }
+    const bool more = nc < K;
+    uint32_t na[H], nb[H];
+    bool nvalid = false;
+    if (more) load(nc, ns, na, nb, nvalid);
+    compiler_fence();
+    sfor<0, H>([&](auto P) { b[decltype(P)::value] = valid ? b[decltype(P)::value] : 0u; });
+    if (c + 1 < K)
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+    else
+      blk_cols<H, 0, H - 1, false>(cols, a, b);
+    if (nc != c) {
+      uint32_t o[H];
+      blk_emit2<H>(cols, carry, o);  // the carry out of block K-1 is dropped: mod R
+      st_rows<H>(ws, Lay::Q + c * H, o);
+    }
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    s = ns;
+    valid = nvalid;
+    sfor<0, H>([&](auto P) {
+      a[decltype(P)::value] = na[decltype(P)::value];
+      b[decltype(P)::value] = nb[decltype(P)::value];
+    });
+  }
+}
+
+template <int H, int K, bool TRUNC>
+__device__ __forceinline__ void scan2_qn(const LaneBuf& ws, const LaneBuf& cn) {
+  using Lay = BlkLayout<H, K>;
+  const uint32_t r = threadIdx.x & 1u;
+  const uint32_t tmask = r == 0u ? 0xFFFFFFFFu : 0u;  // T is added in one lane of the pair
+  uint64_t cols[2 * H];
+  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  uint64_t carry = 0;
+  constexpr uint32_t c0 = TRUNC ? K - 1 : 0;
+  if constexpr (TRUNC && K >= 2) {
+#pragma nounroll
+    for (uint32_t i = 0; i + 2 <= K; ++i)
+      cols[H - 2] += (uint64_t)(ws.ld(Lay::Q + i * H + H - 1) & tmask) * cn.ld((K - 2 - i) * H + H - 1);
+  }
+  auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[H], bool& valid) {
+    const uint32_t k = 2 * s + r;
+    valid = k < diag_pairs<K>(c, false);
+    const uint32_t i = diag_ilo<K>(c) + (valid ? k : 0u);
+    ld_rows<H>(blk_view(ws, i, H), Lay::Q, x);
+    ld_rows<H>(blk_view(cn, c - i, H), 0, y);
+  };
+  uint32_t a[H], b[H];
+  bool valid;
+  load(c0, 0, a, b, valid);
+  uint32_t c = c0, s = 0;
+#pragma nounroll
+  for (;;) {
+    uint32_t nc = c, ns = s + 1;
+    if (2 * ns >= diag_pairs<K>(c, false)) {
+      nc = c + 1;
+      ns = 0;
+    }
+    const bool more = nc < 2 * K - 1;
+    uint32_t na[H], nb[H];
+    bool nvalid = false;
+    if (more) load(nc, ns, na, nb, nvalid);
+    compiler_fence();
+    sfor<0, H>([&](auto P) { b[decltype(P)::value] = valid ? b[decltype(P)::value] : 0u; });
+    if (TRUNC && c == K - 1)
+      blk_cols<H, H - 2, 2 * H - 2, false>(cols, a, b);
+    else
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+    if (nc != c) {  // diagonal c done: add block c of T, then emit or fold the carry
+      uint32_t tb[H];
+      ld_rows<H>(ws, Lay::T + c * H, tb);
+      sfor<0, H>([&](auto D) { cols[decltype(D)::value] += tb[decltype(D)::value] & tmask; });
+      uint32_t o[H];
+      if (TRUNC && c == K - 1) {
+        const uint64_t a2 = pair_sum(cols[H - 2]);
+        const uint64_t a1 = pair_sum(cols[H - 1]) + (a2 >> kLimbBits);
+        carry = (a1 >> kLimbBits) + ((((uint32_t)a1 | (uint32_t)a2) & kLimbMask) != 0u ? 1u : 0u);
+        sfor<0, H>([&](auto D) {
+          constexpr int d = decltype(D)::value;
+          cols[d] = cols[d + H];
+          cols[d + H] = 0;
+        });
+      } else if (c < K) {  // PLAIN, low columns: they vanish mod 2^28
+        blk_emit2<H>(cols, carry, o);
+      } else {
+        blk_emit2<H>(cols, carry, o);
+        st_rows<H>(ws, Lay::Y + (c - K) * H, o);
+      }
+    }
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    s = ns;
+    valid = nvalid;
+    sfor<0, H>([&](auto P) {
+      a[decltype(P)::value] = na[decltype(P)::value];
+      b[decltype(P)::value] = nb[decltype(P)::value];
+    });
+  }
+  uint32_t tb[H];
+  ld_rows<H>(ws, Lay::T + (2 * K - 1) * H, tb);
+  sfor<0, H>([&](auto D) { cols[decltype(D)::value] += tb[decltype(D)::value] & tmask; });
+  uint32_t o[H];
+  blk_emit2<H>(cols, carry, o);
+  st_rows<H>(ws, Lay::Y + (K - 1) * H, o);
+}
+
 // One Montgomery product on the workspace: Y <- REDC(Y * B) or REDC(Y^2).
-// n = K H; context blocks come from the limb-major context arrays.
-template <int H, int K, bool TRUNC, bool KARA = false>
+// n = K H; context blocks come from the limb-major context arrays.  LP lanes
+// per instance (1, or 2 for the schoolbook product).
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1>
 __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const LaneBuf& cn, const LaneBuf& cnp) {
-  // ---- product T = Y * B (or Y^2): Section 2 at block level, or Section 3 --
-  if constexpr (KARA)
-    kara_product<H, K>(sqr, ws);
-  else
-    scan_product<H, K>(sqr, ws);
-  // ---- q = T_lo * N' mod R: pairs i + j <= K - 1 (Algorithm 6 step 1) ------
-  scan_q<H, K>(ws, cnp);
-  // ---- C = (T + q N) / R, truncated (Theorem 2) or whole (Algorithm 3) -----
-  scan_qn<H, K, TRUNC>(ws, cn);
+  static_assert(LP == 1 || (LP == 2 && !KARA), "two lanes per instance: schoolbook products only");
+  if constexpr (LP == 2) {
+    scan2_product<H, K>(sqr, ws);
+    scan2_q<H, K>(ws, cnp);
+    scan2_qn<H, K, TRUNC>(ws, cn);
+  } else {
+    // ---- product T = Y * B (or Y^2): Section 2 at block level, or Section 3 --
+    if constexpr (KARA)
+      kara_product<H, K>(sqr, ws);
+    else
+      scan_product<H, K>(sqr, ws);
+    // ---- q = T_lo * N' mod R: pairs i + j <= K - 1 (Algorithm 6 step 1) ------
+    scan_q<H, K>(ws, cnp);
+    // ---- C = (T + q N) / R, truncated (Theorem 2) or whole (Algorithm 3) -----
+    scan_qn<H, K, TRUNC>(ws, cn);
+  }
 }
 
 // Loads the RW-word little-endian value at src into rows row .. row+n-1 (28-bit limbs).
@@ -573,9 +824,10 @@ __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __r
 }
 
 // ---- modexp, block version (same schedule as k_modexp) ----------------------
-// tws: this wavefront's own workspace region (BlkLayout rows(w) rows of 64
-// lanes, 256 bytes per row), contiguous in memory.
-template <int H, int K, bool TRUNC, bool KARA = false>
+// A tile is 64 / LP instances (LP lanes per instance).  tws: this
+// wavefront's own workspace region (BlkLayout rows(w) rows of 64 / LP
+// instances, 256 / LP bytes per row), contiguous in memory.
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1>
 __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
                                                 const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                 uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
@@ -583,12 +835,14 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
                                                 uint32_t tws_bytes, uint32_t coff, uint32_t tile0) {
   using Lay = BlkLayout<H, K>;
   constexpr uint32_t n = Lay::n;
-  const uint32_t gid = tile0 + (threadIdx.x & 63u);
+  const uint32_t slot = (threadIdx.x & 63u) / LP;  // this lane's instance within the tile
+  const uint32_t gid = tile0 + slot;
   const bool live = gid < count;
+  const bool writer = live && (threadIdx.x % LP) == 0u;  // the lanes of an instance hold equal results
   const uint32_t inst = live ? gid : count - 1;
   uint32_t c = cidx ? cidx[inst] : inst + coff;
   c = c < ctx.count ? c : 0u;
-  const LaneBuf ws{make_buf(tws, tws_bytes), (threadIdx.x & 63u) * 4u, 256u};
+  const LaneBuf ws{make_buf(tws, tws_bytes), slot * 4u, 256u / LP};
   const uint32_t cbytes = n * ctx.stride * 4u;
   const LaneBuf cn{make_buf(ctx.n, cbytes), c * 4u, ctx.stride * 4u};
   const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
@@ -668,7 +922,7 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
 #pragma nounroll
       for (uint32_t i = 0; i < n; ++i) ws.st(Lay::B + i, i == 0 ? 1u : 0u);
     }
-    mont_blk<H, K, TRUNC, KARA>(kind == kSqr, ws, cn, cnp);
+    mont_blk<H, K, TRUNC, KARA, LP>(kind == kSqr, ws, cn, cnp);
     if (store_e >= 0) copy_rows<H>(ws, Lay::G + (uint32_t)store_e * n, ws, Lay::Y, n);
   }
   // canonical result: subtract N once if Y >= N (constant time)
@@ -680,21 +934,21 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
     br = v >> kLimbBits;
   }
   const uint32_t src = br != 0 ? Lay::Y : Lay::B;
-  if (live) contract_rows<H, K>(ws, src, out + (size_t)inst * bw, bw);
+  if (writer) contract_rows<H, K>(ws, src, out + (size_t)inst * bw, bw);
 }
 
-template <int H, int K, bool TRUNC, bool KARA = false>
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1>
 __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                    const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                    uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
                                                    uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
                                                    uint32_t ws_bytes, uint32_t coff) {
-  const uint32_t tile0 = blockIdx.x * 64;
-  const uint32_t tbytes = BlkLayout<H, K>::rows(w) * 256u;  // this block's region
+  const uint32_t tile0 = blockIdx.x * (64u / LP);
+  const uint32_t tbytes = BlkLayout<H, K>::rows(w) * (256u / LP);  // this block's region
   if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
   stagger<H * K>(blockIdx.x, w);
-  modexp_tile_blk<H, K, TRUNC, KARA>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
-                                     ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0);
+  modexp_tile_blk<H, K, TRUNC, KARA, LP>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
+                                         ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0);
 }
 
 }  // namespace mx

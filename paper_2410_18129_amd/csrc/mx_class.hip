@@ -22,6 +22,9 @@ constexpr int kW = words_for(kBits);                      // canonical values (<
 constexpr int kRW = words_for(28 * kN);                   // Montgomery-domain values (< 2N < R)
 
 static_assert(!kHasBlk || (kK >= 1 && kK <= 4), "block kernels: redundant limbs need K <= 4");
+// block exponentiations of at most this many instances run two lanes per
+// instance: 65536 lanes = one wavefront on each of MI355X's 1024 SIMDs
+constexpr uint32_t kTwoLaneMax = 32768;
 
 hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
   const uint32_t blocks = (ctx.count + 63) / 64;
@@ -105,6 +108,18 @@ hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* ci
   }
   if constexpr (kBlock || kHasBlk) {
     if (kBlock || impl == 1) {
+      // a batch that leaves SIMDs without a wavefront runs two lanes per instance
+      // (half the latency, twice the lanes); the workspace has room for either
+      if (count <= kTwoLaneMax) {
+        const uint32_t blocks2 = (count + 31) / 32;
+        if (trunc)
+          hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, false, 2>), dim3(blocks2), dim3(64), 0, st, ctx, cidx, base,
+                             ex, ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
+        else
+          hipLaunchKernelGGL((k_modexp_blk<kH, kK, false, false, 2>), dim3(blocks2), dim3(64), 0, st, ctx, cidx,
+                             base, ex, ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
+        return hipGetLastError();
+      }
       if (trunc)
         hipLaunchKernelGGL((k_modexp_blk<kH, kK, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
                            ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);

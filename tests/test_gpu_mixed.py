@@ -62,6 +62,28 @@ def test_block_kernel_small_and_large_windows(mx, window):
     ctx.close()
 
 
+def test_block_kernel_one_and_two_lanes_per_instance_agree(mx):
+    # batches of at most 32768 instances run two lanes per instance, larger ones one: the same
+    # instances computed both ways (a 33001-instance batch and a 4000-instance slice of it)
+    bits, n = 1024, 33001
+    mods = wl.random_moduli(wl.stream(13, "moduli"), bits, n)
+    ctx = mx.Context(mods, bits)
+    base = wl.random_below_fast(wl.stream(13, "bases"), mods, bits)
+    exps = wl.random_exponents(wl.stream(13, "exps"), bits, n)
+    bd, ed = mx.to_device(base), mx.to_device(exps)
+    one = dev_ints(mx.modexp(ctx, bd, ed, bits, window=3, block=True))
+    import torch
+    lo, hi = 29000, 33001
+    idx = torch.arange(lo, hi, dtype=torch.int32, device=bd.device)
+    two = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
+                             ctx_idx=idx))
+    assert two == one[lo:hi]
+    M, Bs, Es = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
+    for i in (0, 32767, 32768, n - 1):
+        assert one[i] == oracle.modexp(Bs[i], Es[i], M[i], bits)
+    ctx.close()
+
+
 def test_block_flag_unsupported_class(mx):
     ctx = mx.Context(wl.random_moduli(wl.stream(12, "moduli"), 256, 1), 256)
     a = ints_dev([1], ctx.mont_words)
