@@ -41,6 +41,7 @@ struct MixedBatch {
   uint64_t* out;
   uint32_t* ws;   // one region of rows x 64 words per persistent wave
   uint32_t count, ebits, ewords, w, family, rows;
+  uint32_t lanes;  // lanes per instance: tiles of 64 / lanes instances
 };
 
 struct MixedArgs {
@@ -67,8 +68,8 @@ __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
     if (j >= args.njobs) break;  // every wave leaves once the list is exhausted
     const uint32_t job = args.jobs[j];
     const MixedBatch& mb = args.b[job >> 28];
-    const uint32_t tile0 = (job & 0x0FFFFFFFu) * 64u;
-    const uint32_t tb = mb.rows * 256u;                         // this wave's region of the batch's workspace
+    const uint32_t tile0 = (job & 0x0FFFFFFFu) * (64u / mb.lanes);
+    const uint32_t tb = mb.rows * (256u / mb.lanes);            // this wave's region of the batch's workspace
     uint32_t* const tw = mb.ws + (size_t)blockIdx.x * (tb / 4u);
     switch (mb.family) {
       case kF1024:
@@ -99,9 +100,13 @@ __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
         modexp_tile_blk<37, 4, true, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u, mb.out,
                                            mb.count, tw, tb, 0u, tile0);
         break;
-      default:
-        modexp_tile_blk<37, 4, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u, mb.out,
-                                     mb.count, tw, tb, 0u, tile0);
+      default:  // 4096 bits, schoolbook: two lanes per instance (these tiles bound the launch's length)
+        if (mb.lanes == 2)
+          modexp_tile_blk<37, 4, true, false, 2>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u,
+                                                 mb.out, mb.count, tw, tb, 0u, tile0);
+        else
+          modexp_tile_blk<37, 4, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u, mb.out,
+                                       mb.count, tw, tb, 0u, tile0);
         break;
     }
   }
@@ -182,7 +187,8 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     if (d.n && (!d.base || !d.out || (d.exp_bits && !d.exp))) return mx_fail(MX_EINVAL, "batch %u: NULL pointer", b);
     if (!d.ctx_idx && d.n > d.ctx->count) return mx_fail(MX_EINVAL, "batch %u: n exceeds the context count", b);
     if (d.window > 8) return mx_fail(MX_EINVAL, "batch %u: window outside 1..8", b);
-    total_tiles += (d.n + 63) / 64;
+    const uint32_t per_tile = fam[b] == mx::kF4096B ? 32u : 64u;  // two lanes per 4096-bit instance
+    total_tiles += (d.n + per_tile - 1) / per_tile;
   }
   if (total_tiles >= (1u << 28)) return mx_fail(MX_EINVAL, "mx_mixed_plan_create: too many tiles");
   mx_mixed_plan* p = new (std::nothrow) mx_mixed_plan;
@@ -227,13 +233,18 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     mb.w = w;
     mb.family = fam[b];
     mb.rows = rows;
-    const float est = (float)c->limbs * c->limbs * (float)(d.exp_bits ? d.exp_bits : 1);
+    // the longest tiles (4096-bit schoolbook) run two lanes per instance: their tile
+    // takes about 0.8 of the one-lane time, so the launch is not bound by them
+    mb.lanes = fam[b] == mx::kF4096B ? 2u : 1u;
+    const uint32_t per_tile = 64u / mb.lanes;
+    const float est = (float)c->limbs * c->limbs * (float)(d.exp_bits ? d.exp_bits : 1) * (mb.lanes == 2 ? 0.8f : 1.f);
     const float cost = d.tile_cost > 0.f ? d.tile_cost : est;
-    for (uint32_t t = 0; t < (d.n + 63) / 64; ++t) tiles.push_back({cost, (b << 28) | t});
+    for (uint32_t t = 0; t < (d.n + per_tile - 1) / per_tile; ++t) tiles.push_back({cost, (b << 28) | t});
   }
   std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& x, const Tile& y) { return x.cost > y.cost; });
   std::vector<uint32_t> jobs(tiles.size());
   for (size_t i = 0; i < tiles.size(); ++i) jobs[i] = tiles[i].code;
+  if (e == hipSuccess && jobs.size() != p->njobs) e = hipErrorInvalidValue;  // the kernel reads njobs entries
   if (e == hipSuccess) e = hipMalloc(&p->d_jobs, std::max<size_t>(jobs.size(), 1) * sizeof(uint32_t));
   if (e == hipSuccess && !jobs.empty())
     e = hipMemcpy(p->d_jobs, jobs.data(), jobs.size() * sizeof(uint32_t), hipMemcpyHostToDevice);

@@ -110,11 +110,13 @@ def _mixed_inputs(mx, counts, k=13):
 
 def test_mixed_plan_matches_single_class_and_oracle(mx):
     import torch
-    counts = {1024: 130, 2048: 70, 3072: 65, 4096: 64}
+    counts = {1024: 130, 2048: 70, 3072: 65, 4096: 71}
     batches, ref = _mixed_inputs(mx, counts)
     batches[1]["block"] = False
     plan = mx.MixedPlan(batches)
-    assert plan.njobs == sum((n + 63) // 64 for n in counts.values())
+    # tiles of 64 instances; 4096-bit schoolbook tiles hold 32 (two lanes per instance)
+    assert plan.njobs == sum((n + (31 if bits == 4096 else 63)) // (32 if bits == 4096 else 64)
+                             for bits, n in counts.items())
     plan.launch()
     torch.cuda.synchronize()
     for b, (mods, base, exps), bits in zip(batches, ref, counts):
