@@ -57,9 +57,14 @@ enum {
   MX_IMPL_BLOCK = 2, /* block-level schoolbook over 37-limb blocks for the
                         1024/2048 classes (the only kernels above 2048 bits);
                         same results, MX_EUNSUPPORTED where not built        */
-  MX_MUL_KARATSUBA = 4 /* block kernels whose product (A*B or A^2) is one-level
-                          Karatsuba over half-size block numbers (Section 3):
-                          2048 and 4096 bits; same results                   */
+  MX_MUL_KARATSUBA = 4, /* block kernels whose product (A*B or A^2) is one-level
+                           Karatsuba over half-size block numbers (Section 3):
+                           2048 and 4096 bits; same results                  */
+  MX_ONE_LANE = 8      /* exponentiation with the block kernels: one lane per
+                          instance even for batches of at most 32768 (which
+                          otherwise run two lanes per instance: lower latency,
+                          twice the lanes); for loaded devices where throughput
+                          matters more than latency; same results           */
 };
 
 /* Montgomery contexts for `count` moduli of size class `bits` (Section 4:

@@ -83,11 +83,12 @@ static mx_status ensure_ws(mont_ctx* ctx, size_t need, const char* name) {
   return MX_OK;
 }
 
-// Kernel family for the flags: 0 register-resident, 1 block, 2 block + Karatsuba; -1 if not built.
+// Kernel family for the flags: 0 register-resident, 1 block, 2 block + Karatsuba, 3 block with one
+// lane per instance whatever the batch size (MX_ONE_LANE); -1 if not built.
 static int impl_of(const mont_ctx* ctx, uint32_t flags) {
   if (flags & MX_MUL_KARATSUBA) return ctx->ops->has_kara ? 2 : -1;
-  if (flags & MX_IMPL_BLOCK) return ctx->ops->has_block ? 1 : -1;
-  return 0;
+  if (flags & MX_IMPL_BLOCK) return ctx->ops->has_block ? ((flags & MX_ONE_LANE) ? 3 : 1) : -1;
+  return (flags & MX_ONE_LANE) && ctx->bits > 2048 ? 3 : 0;
 }
 
 // Instances per launch so that rows * padded count * 4 bytes fits one descriptor.
@@ -258,7 +259,7 @@ static mx_status modexp_common(const char* name, mont_ctx* ctx, const uint32_t* 
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!base || !out || (exp_bits && !exp)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA))
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
   const int impl = impl_of(ctx, flags);
   if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);

@@ -35,6 +35,7 @@ hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
 // per-lane workspace words: block classes keep Y, B, T, Q, S (and the table)
 // in memory; register-resident classes need only the exponentiation table
 uint32_t ws_rows_fn(int impl, bool modexp, uint32_t w) {
+  // impl: 0 register-resident, 1 block, 2 block + Karatsuba, 3 block with one lane per instance
   if (kBlock || (kHasBlk && impl >= 1)) return modexp ? BlkLayout<kH, kK>::rows(w) : BlkLayout<kH, kK>::G;
   (void)impl;
   return modexp ? (1u << w) * (uint32_t)packed_words(kN) : 0u;  // densely packed table entries
@@ -107,10 +108,11 @@ hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* ci
     }
   }
   if constexpr (kBlock || kHasBlk) {
-    if (kBlock || impl == 1) {
+    if (kBlock || impl == 1 || impl == 3) {
       // a batch that leaves SIMDs without a wavefront runs two lanes per instance
-      // (half the latency, twice the lanes); the workspace has room for either
-      if (count <= kTwoLaneMax) {
+      // (lower latency, twice the lanes) unless one lane was asked for (impl 3);
+      // the workspace has room for either
+      if (count <= kTwoLaneMax && impl != 3) {
         const uint32_t blocks2 = (count + 31) / 32;
         if (trunc)
           hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, false, 2>), dim3(blocks2), dim3(64), 0, st, ctx, cidx, base,

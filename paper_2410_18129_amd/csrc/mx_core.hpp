@@ -164,7 +164,7 @@ __device__ __forceinline__ void colblock(const uint32_t (&a)[NA], const uint32_t
 // the products that use them, so that the latency of a group's reads is
 // covered by the previous group's products (one wavefront per SIMD has no
 // other wavefront to switch to).
-constexpr int kPrefetch = 8;
+constexpr int kPrefetch = 16;
 
 template <int K0, int BK, int ILO, int IHI, int JLO, int JHI, typename M, int NA, typename Ld>
 __device__ __forceinline__ void colblock_ld(const uint32_t (&a)[NA], Ld&& ld, uint64_t (&acc)[BK]) {

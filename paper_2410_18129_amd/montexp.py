@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmontexp.so")
 
 MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EUNSUPPORTED = 0, 1, 2, 3, 4
-MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA = 0, 1, 2, 4
+MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA, MX_ONE_LANE = 0, 1, 2, 4, 8
 SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
@@ -223,8 +223,11 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=Fal
     return out
 
 
-def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None, block=False):
-    """base^exp mod N per instance; base: int64 [n, words], exp: int64 [n, ceil(exp_bits/64)]."""
+def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None, block=False,
+           one_lane=False):
+    """base^exp mod N per instance; base: int64 [n, words], exp: int64 [n, ceil(exp_bits/64)].
+
+    one_lane: block kernels keep one lane per instance for small batches too (MX_ONE_LANE)."""
     n = base.shape[0]
     if out is None:
         import torch
@@ -234,7 +237,7 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
     if exp_bits:
         _check_rows("exp", exp, n, words_for(exp_bits))
     _check_idx(ctx_idx, n, ctx)
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block)
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0)
     _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,
                               window, _ptr(out), n, flags, _stream_ptr(stream)))
     return out
@@ -305,7 +308,7 @@ def modexp_ws_bytes(ctx, n, window=0, block=False):
 
 
 def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, plain=False, stream=None,
-              block=False, n=None):
+              block=False, n=None, one_lane=False):
     """modexp with a caller-owned workspace tensor (uint8/any dtype, device); n rows of base/exp used."""
     n = base.shape[0] if n is None else n
     if out is None:
@@ -324,7 +327,7 @@ def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, pl
         raise ValueError("n exceeds the context count (pass ctx_idx)")
     if not ws.is_cuda or not ws.is_contiguous():
         raise ValueError("ws: expected a contiguous device tensor")
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block)
+    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0)
     _check(lib().modexp_batch_ws(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None,
                                  exp_bits, window, _ptr(out), n, flags, _ptr(ws), ws.numel() * ws.element_size(),
                                  _stream_ptr(stream)))

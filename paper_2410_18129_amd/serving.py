@@ -209,9 +209,10 @@ class GpuExecutor:
     queue.
     """
 
-    def __init__(self, trace, max_batch, mem_budget, windows=None, max_slots=4, device="cuda"):
+    def __init__(self, trace, max_batch, mem_budget, windows=None, max_slots=4, device="cuda", one_lane_from=16384):
         import torch
         self.torch = torch
+        self.one_lane_from = one_lane_from
         self.classes = trace.classes
         self.ctx = {c: mx.Context(trace.mods[c], c) for c in self.classes}
         self.windows = windows or {c: 0 for c in self.classes}
@@ -243,8 +244,11 @@ class GpuExecutor:
     def launch(self, slot, c, lo, hi):
         torch = self.torch
         st = slot["stream"]
+        # a large batch means a loaded device: the block kernels then keep one lane per
+        # instance (throughput); small batches run two lanes per instance (latency)
         mx.modexp_ws(self.ctx[c], self.base[c][lo:hi], self.exp[c][lo:hi], c, slot["ws"], window=self.windows[c],
-                     out=self.out[c][lo:hi], ctx_idx=self.cidx[c][lo:hi], stream=st)
+                     out=self.out[c][lo:hi], ctx_idx=self.cidx[c][lo:hi], stream=st,
+                     one_lane=hi - lo >= self.one_lane_from)
         ev = torch.cuda.Event()
         ev.record(st)
         slot["event"] = ev

@@ -78,6 +78,9 @@ def test_block_kernel_one_and_two_lanes_per_instance_agree(mx):
     two = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
                              ctx_idx=idx))
     assert two == one[lo:hi]
+    forced = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
+                                ctx_idx=idx, one_lane=True))  # MX_ONE_LANE: one lane per instance at any size
+    assert forced == one[lo:hi]
     M, Bs, Es = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
     for i in (0, 32767, 32768, n - 1):
         assert one[i] == oracle.modexp(Bs[i], Es[i], M[i], bits)
