@@ -1,7 +1,7 @@
 """Limb-level model of the truncated Montgomery reduction -- TEST INFRASTRUCTURE.
 
 Written from Section 5 (Algorithm 6, Theorem 1, Theorem 2 and equations
-(1)-(5)).  It is a checker of the *reading* of the paper, not part of the GPU
+(1)-(5)); ``redc_cios`` from Section 4 (Algorithm 4).  It is a checker of the *reading* of the paper, not part of the GPU
 library, and shares nothing with it.
 
 Setting: limbs of L bits, R = 2^(L*n), N odd with 4N <= R, T < 4N^2,
@@ -164,6 +164,39 @@ def redc_truncated_fullcol(T, N, L, n):
     return (T >> (L * n)) + H + k
 
 
+def redc_cios(A, B, N, L, n):
+    """Algorithm 4 (word-interleaved, CIOS): returns (A*B*R^{-1} as REDC gives it, largest column sum).
+
+    For each limb a_i of A: Y += a_i * B; q_i = (Y mod 2^L) * N'_0 mod 2^L
+    with N'_0 = -N^{-1} mod 2^L; Y = (Y + q_i * N) / 2^L.  Y is held as
+    column sums that are never normalised inside the loop: after adding
+    q_i * N the lowest column is divisible by 2^L, and only its carry moves
+    up with the shift.  The q_i are the limbs of q = -A*B*N^{-1} mod R, so the
+    result is (A*B + q*N) / R, the exact Montgomery integer of Algorithm 5.
+    The peak column sum bounds the accumulator width a word-sliced
+    implementation needs.
+    """
+    B_ = 1 << L
+    M = B_ - 1
+    al, bl, Nl = limbs(A, L, n), limbs(B, L, n), limbs(N, L, n)
+    n0 = (-pow(N, -1, B_)) % B_
+    Y = [0] * (n + 1)
+    peak = 0
+    for i in range(n):
+        for j in range(n):
+            Y[j] += al[i] * bl[j]
+        qi = ((Y[0] & M) * n0) & M
+        for j in range(n):
+            Y[j] += qi * Nl[j]
+        peak = max(peak, max(Y))
+        assert Y[0] & M == 0
+        carry = Y[0] >> L
+        Y = Y[1:] + [0]
+        Y[0] += carry
+    peak = max(peak, max(Y))
+    return sum(y << (L * j) for j, y in enumerate(Y)), peak
+
+
 def fullcol_condition(L, n):
     """True when the carry window of redc_truncated_fullcol is provably wide enough."""
     return (n - 2) * ((1 << L) + 2) + 1 <= (1 << (2 * L))
@@ -173,10 +206,14 @@ def counts(n):
     """Partial products (L x L -> 2L) per operation, from the schedules above.
 
     plain: full product + low-half q + full q*N; truncated: the q*N part keeps
-    only weights >= n-2 (hi) / >= n-1 (lo), i.e. n(n+1)/2 + n - 1 products.
+    only weights >= n-2 (hi) / >= n-1 (lo), i.e. n(n+1)/2 + n - 1 products;
+    CIOS (Algorithm 4): n products a_i*b_j and n products q_i*N_j per limb of A,
+    plus one product for q_i, for squares too.
     """
     tri = n * (n + 1) // 2
     return {
+        "mul_cios": 2 * n * n + n,
+        "sqr_cios": 2 * n * n + n,
         "mul_plain": n * n + tri + n * n,
         "sqr_plain": tri + tri + n * n,
         "mul_trunc": n * n + tri + tri + n - 1,

@@ -99,3 +99,57 @@ def test_counts_formulas():
     for n in (2, 3, 7, 33):
         cnt = sum(1 for i in range(n) for j in range(n) if i + j >= n - 2)
         assert cnt == n * (n + 1) // 2 + n - 1
+
+
+def _cios_operands(L, n, cap):
+    """Odd N <= R/4 and operand pairs A, B < 2N (evenly spaced, plus the extremes)."""
+    R = 1 << (L * n)
+    for N in range(3, R // 4 + 1, 2):
+        lim = 2 * N
+        step = max(1, lim // cap)
+        vals = list(range(0, lim, step)) + [lim - 1]
+        for A in vals:
+            for B in vals:
+                yield N, A, B
+
+
+@pytest.mark.parametrize("L,n", SMALL)
+def test_cios_equals_exact_redc_exhaustive(L, n):
+    """Algorithm 4 with lazy column sums returns the exact Montgomery integer (AB + qN)/R."""
+    for N, A, B in _cios_operands(L, n, 24):
+        got, _ = m.redc_cios(A, B, N, L, n)
+        assert got == m.redc_exact(A * B, N, L, n), (L, n, N, A, B)
+
+
+@pytest.mark.parametrize("n", [3, 10, 37, 74])
+def test_cios_random_at_28bit_limbs_and_column_bound(n):
+    """At the library's limb width the lazy column sums stay below 2n 2^(2L), within 64 bits up to n = 127."""
+    rng = random.Random(300 + n)
+    L = 28
+    t = L * n - 2
+    worst = 0
+    for trial in range(12):
+        if trial < 3:
+            # every limb of N at its maximum below 2^t: the largest q_i N_j products
+            N = (1 << t) - 1
+        else:
+            N = rng.getrandbits(t) | 1 | (1 << (t - 1))
+        ops = [(2 * N - 1, 2 * N - 1), (0, 2 * N - 1), (1, 1)]
+        A, B = ops[trial] if trial < 3 else (rng.randrange(2 * N), rng.randrange(2 * N))
+        got, peak = m.redc_cios(A, B, N, L, n)
+        e = m.redc_exact(A * B, N, L, n)
+        assert got == e == oracle.redc(A * B, N, L * n)
+        assert e < 2 * N
+        worst = max(worst, peak)
+    assert worst < 2 * n * (1 << (2 * L))
+    assert 2 * 127 * (1 << (2 * L)) <= 1 << 64
+
+
+def test_cios_and_truncated_counts():
+    """CIOS needs 2n^2 + n products for a product and a square alike; truncation wins on squares."""
+    for n in (37, 74):
+        c = m.counts(n)
+        assert c["mul_cios"] == c["sqr_cios"] == 2 * n * n + n
+        assert c["sqr_trunc"] < c["sqr_cios"]
+        # the multiplication counts differ by n - 1: 2n^2 + 2n - 1 against 2n^2 + n
+        assert c["mul_trunc"] - c["mul_cios"] == n - 1
