@@ -62,9 +62,10 @@ enum {
                            2048 and 4096 bits; same results                  */
   MX_ONE_LANE = 8      /* exponentiation with the block kernels: one lane per
                           instance even for batches of at most 32768 (which
-                          otherwise run two lanes per instance: lower latency,
-                          twice the lanes); for loaded devices where throughput
-                          matters more than latency; same results           */
+                          otherwise run four lanes per instance up to 16384
+                          and two up to 32768: lower latency, more lanes); for
+                          loaded devices where throughput matters more than
+                          latency; same results                              */
 };
 
 /* Montgomery contexts for `count` moduli of size class `bits` (Section 4:

@@ -498,32 +498,42 @@ __device__ __forceinline__ void scan_qn(const LaneBuf& ws, const LaneBuf& cn) {
   st_rows<H>(ws, Lay::Y + (K - 1) * H, o);
 }
 
-// ---- two lanes per instance ------------------------------------------------
+// ---- several lanes per instance --------------------------------------------
 //
-// For batches too small to give every SIMD a wavefront, lanes 2m and 2m+1
-// hold the same instance and halve its latency.  The block pairs of each
-// diagonal are dealt to the two lanes alternately (a lane left without a
-// pair in a diagonal's last slot multiplies by zero); each lane accumulates
-// its own partial column sums, and when a diagonal's low columns are emitted
-// the two partial sums are added across the lane pair (a DPP swap of
-// adjacent lanes), so both lanes normalise the same totals and write the
-// same limbs.  Square blocks are formed as whole block products here (the
-// partner lane may be running a cross pair in the same instructions).
+// For batches too small to give every SIMD a wavefront, LP = 2 or 4
+// consecutive lanes hold the same instance and cut its latency.  The block
+// pairs of each diagonal are dealt to the group's lanes in turn (a lane left
+// without a pair in a diagonal's last slot multiplies by zero); each lane
+// accumulates its own partial column sums, and when a diagonal's low columns
+// are emitted the partial sums are added across the group (DPP swaps inside
+// a quad of lanes), so all lanes of the group normalise the same totals and
+// write the same limbs.  Square blocks are formed as whole block products
+// here (another lane of the group may be running a cross pair in the same
+// instructions).
 
-// v + the same variable of the partner lane (lanes 2m, 2m+1)
-__device__ __forceinline__ uint64_t pair_sum(uint64_t v) {
+// v + the same 64-bit variable of the other lanes of this lane's group of LP
+// consecutive lanes (LP = 1, 2 or 4)
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_add64(uint64_t v) {
   const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
-  const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
-  const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+  const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
   return v + (((uint64_t)phi << 32) | plo);
 }
+template <int LP>
+__device__ __forceinline__ uint64_t group_sum(uint64_t v) {
+  static_assert(LP == 1 || LP == 2 || LP == 4, "lane groups of 1, 2 or 4");
+  if constexpr (LP >= 2) v = dpp_add64<0xB1>(v);  // quad_perm [1,0,3,2]: swap adjacent lanes
+  if constexpr (LP == 4) v = dpp_add64<0x4E>(v);  // quad_perm [2,3,0,1]: swap lane pairs
+  return v;
+}
 
-// blk_emit on the pair's summed columns
-template <int H>
-__device__ __forceinline__ void blk_emit2(uint64_t (&cols)[2 * H], uint64_t& carry, uint32_t (&o)[H]) {
+// blk_emit on the group's summed columns
+template <int H, int LP>
+__device__ __forceinline__ void blk_emitg(uint64_t (&cols)[2 * H], uint64_t& carry, uint32_t (&o)[H]) {
   sfor<0, H>([&](auto D) {
     constexpr int d = decltype(D)::value;
-    const uint64_t v = pair_sum(cols[d]) + carry;
+    const uint64_t v = group_sum<LP>(cols[d]) + carry;
     o[d] = (uint32_t)v & kLimbMask;
     carry = v >> kLimbBits;
   });
@@ -551,17 +561,17 @@ __device__ __forceinline__ uint32_t diag_pairs(uint32_t c, bool sqr) {
   return top - ilo + 1;
 }
 
-template <int H, int K>
-__device__ __forceinline__ void scan2_product(bool sqr, const LaneBuf& ws) {
+template <int H, int K, int LP>
+__device__ __forceinline__ void scang_product(bool sqr, const LaneBuf& ws) {
   using Lay = BlkLayout<H, K>;
   const uint32_t rb = sqr ? Lay::Y : Lay::B;
-  const uint32_t r = threadIdx.x & 1u;
+  const uint32_t r = threadIdx.x % LP;
   uint64_t cols[2 * H];
   sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
-  // slot s of diagonal c: this lane's pair is i = ilo + 2 s + r, if it exists
+  // slot s of diagonal c: this lane's pair is i = ilo + LP s + r, if it exists
   auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[H], uint32_t& sh, bool& valid) {
-    const uint32_t k = 2 * s + r;
+    const uint32_t k = LP * s + r;
     valid = k < diag_pairs<K>(c, sqr);
     const uint32_t i = diag_ilo<K>(c) + (valid ? k : 0u), j = c - i;
     ld_rows<H>(blk_view(ws, i, H), Lay::Y, x);
@@ -575,7 +585,7 @@ __device__ __forceinline__ void scan2_product(bool sqr, const LaneBuf& ws) {
 #pragma nounroll
   for (;;) {
     uint32_t nc = c, ns = s + 1;
-    if (2 * ns >= diag_pairs<K>(c, sqr)) {
+    if (LP * ns >= diag_pairs<K>(c, sqr)) {
       nc = c + 1;
       ns = 0;
     }
@@ -588,7 +598,7 @@ __device__ __forceinline__ void scan2_product(bool sqr, const LaneBuf& ws) {
     blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
     if (nc != c) {
       uint32_t o[H];
-      blk_emit2<H>(cols, carry, o);
+      blk_emitg<H, LP>(cols, carry, o);
       st_rows<H>(ws, Lay::T + c * H, o);
     }
     compiler_fence();
@@ -603,20 +613,20 @@ __device__ __forceinline__ void scan2_product(bool sqr, const LaneBuf& ws) {
     });
   }
   uint32_t o[H];
-  blk_emit2<H>(cols, carry, o);
+  blk_emitg<H, LP>(cols, carry, o);
   st_rows<H>(ws, Lay::T + (2 * K - 1) * H, o);
   ws.st(Lay::T + 2 * Lay::n, (uint32_t)carry);
 }
 
-template <int H, int K>
-__device__ __forceinline__ void scan2_q(const LaneBuf& ws, const LaneBuf& cnp) {
+template <int H, int K, int LP>
+__device__ __forceinline__ void scang_q(const LaneBuf& ws, const LaneBuf& cnp) {
   using Lay = BlkLayout<H, K>;
-  const uint32_t r = threadIdx.x & 1u;
+  const uint32_t r = threadIdx.x % LP;
   uint64_t cols[2 * H];
   sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
   auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[H], bool& valid) {
-    const uint32_t k = 2 * s + r;
+    const uint32_t k = LP * s + r;
     valid = k <= c;
     const uint32_t i = valid ? k : 0u;
     ld_rows<H>(blk_view(ws, i, H), Lay::T, x);
@@ -629,7 +639,7 @@ __device__ __forceinline__ void scan2_q(const LaneBuf& ws, const LaneBuf& cnp) {
 #pragma nounroll
   for (;;) {
     uint32_t nc = c, ns = s + 1;
-    if (2 * ns > c) {
+    if (LP * ns > c) {
       nc = c + 1;
       ns = 0;
     }
@@ -645,7 +655,7 @@ __device__ __forceinline__ void scan2_q(const LaneBuf& ws, const LaneBuf& cnp) {
       blk_cols<H, 0, H - 1, false>(cols, a, b);
     if (nc != c) {
       uint32_t o[H];
-      blk_emit2<H>(cols, carry, o);  // the carry out of block K-1 is dropped: mod R
+      blk_emitg<H, LP>(cols, carry, o);  // the carry out of block K-1 is dropped: mod R
       st_rows<H>(ws, Lay::Q + c * H, o);
     }
     compiler_fence();
@@ -660,11 +670,11 @@ __device__ __forceinline__ void scan2_q(const LaneBuf& ws, const LaneBuf& cnp) {
   }
 }
 
-template <int H, int K, bool TRUNC>
-__device__ __forceinline__ void scan2_qn(const LaneBuf& ws, const LaneBuf& cn) {
+template <int H, int K, bool TRUNC, int LP>
+__device__ __forceinline__ void scang_qn(const LaneBuf& ws, const LaneBuf& cn) {
   using Lay = BlkLayout<H, K>;
-  const uint32_t r = threadIdx.x & 1u;
-  const uint32_t tmask = r == 0u ? 0xFFFFFFFFu : 0u;  // T is added in one lane of the pair
+  const uint32_t r = threadIdx.x % LP;
+  const uint32_t tmask = r == 0u ? 0xFFFFFFFFu : 0u;  // T is added in one lane of the group
   uint64_t cols[2 * H];
   sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
@@ -675,7 +685,7 @@ __device__ __forceinline__ void scan2_qn(const LaneBuf& ws, const LaneBuf& cn) {
       cols[H - 2] += (uint64_t)(ws.ld(Lay::Q + i * H + H - 1) & tmask) * cn.ld((K - 2 - i) * H + H - 1);
   }
   auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[H], bool& valid) {
-    const uint32_t k = 2 * s + r;
+    const uint32_t k = LP * s + r;
     valid = k < diag_pairs<K>(c, false);
     const uint32_t i = diag_ilo<K>(c) + (valid ? k : 0u);
     ld_rows<H>(blk_view(ws, i, H), Lay::Q, x);
@@ -688,7 +698,7 @@ __device__ __forceinline__ void scan2_qn(const LaneBuf& ws, const LaneBuf& cn) {
 #pragma nounroll
   for (;;) {
     uint32_t nc = c, ns = s + 1;
-    if (2 * ns >= diag_pairs<K>(c, false)) {
+    if (LP * ns >= diag_pairs<K>(c, false)) {
       nc = c + 1;
       ns = 0;
     }
@@ -708,8 +718,8 @@ __device__ __forceinline__ void scan2_qn(const LaneBuf& ws, const LaneBuf& cn) {
       sfor<0, H>([&](auto D) { cols[decltype(D)::value] += tb[decltype(D)::value] & tmask; });
       uint32_t o[H];
       if (TRUNC && c == K - 1) {
-        const uint64_t a2 = pair_sum(cols[H - 2]);
-        const uint64_t a1 = pair_sum(cols[H - 1]) + (a2 >> kLimbBits);
+        const uint64_t a2 = group_sum<LP>(cols[H - 2]);
+        const uint64_t a1 = group_sum<LP>(cols[H - 1]) + (a2 >> kLimbBits);
         carry = (a1 >> kLimbBits) + ((((uint32_t)a1 | (uint32_t)a2) & kLimbMask) != 0u ? 1u : 0u);
         sfor<0, H>([&](auto D) {
           constexpr int d = decltype(D)::value;
@@ -717,9 +727,9 @@ __device__ __forceinline__ void scan2_qn(const LaneBuf& ws, const LaneBuf& cn) {
           cols[d + H] = 0;
         });
       } else if (c < K) {  // PLAIN, low columns: they vanish mod 2^28
-        blk_emit2<H>(cols, carry, o);
+        blk_emitg<H, LP>(cols, carry, o);
       } else {
-        blk_emit2<H>(cols, carry, o);
+        blk_emitg<H, LP>(cols, carry, o);
         st_rows<H>(ws, Lay::Y + (c - K) * H, o);
       }
     }
@@ -737,20 +747,20 @@ __device__ __forceinline__ void scan2_qn(const LaneBuf& ws, const LaneBuf& cn) {
   ld_rows<H>(ws, Lay::T + (2 * K - 1) * H, tb);
   sfor<0, H>([&](auto D) { cols[decltype(D)::value] += tb[decltype(D)::value] & tmask; });
   uint32_t o[H];
-  blk_emit2<H>(cols, carry, o);
+  blk_emitg<H, LP>(cols, carry, o);
   st_rows<H>(ws, Lay::Y + (K - 1) * H, o);
 }
 
 // One Montgomery product on the workspace: Y <- REDC(Y * B) or REDC(Y^2).
 // n = K H; context blocks come from the limb-major context arrays.  LP lanes
-// per instance (1, or 2 for the schoolbook product).
+// per instance (1, or 2 or 4 for the schoolbook product).
 template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1>
 __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const LaneBuf& cn, const LaneBuf& cnp) {
-  static_assert(LP == 1 || (LP == 2 && !KARA), "two lanes per instance: schoolbook products only");
-  if constexpr (LP == 2) {
-    scan2_product<H, K>(sqr, ws);
-    scan2_q<H, K>(ws, cnp);
-    scan2_qn<H, K, TRUNC>(ws, cn);
+  static_assert(LP == 1 || ((LP == 2 || LP == 4) && !KARA), "several lanes per instance: schoolbook products only");
+  if constexpr (LP > 1) {
+    scang_product<H, K, LP>(sqr, ws);
+    scang_q<H, K, LP>(ws, cnp);
+    scang_qn<H, K, TRUNC, LP>(ws, cn);
   } else {
     // ---- product T = Y * B (or Y^2): Section 2 at block level, or Section 3 --
     if constexpr (KARA)

@@ -22,8 +22,9 @@ constexpr int kW = words_for(kBits);                      // canonical values (<
 constexpr int kRW = words_for(28 * kN);                   // Montgomery-domain values (< 2N < R)
 
 static_assert(!kHasBlk || (kK >= 1 && kK <= 4), "block kernels: redundant limbs need K <= 4");
-// block exponentiations of at most this many instances run two lanes per
-// instance: 65536 lanes = one wavefront on each of MI355X's 1024 SIMDs
+// block exponentiations of at most this many instances run four (two) lanes
+// per instance: 65536 lanes = one wavefront on each of MI355X's 1024 SIMDs
+constexpr uint32_t kFourLaneMax = 16384;
 constexpr uint32_t kTwoLaneMax = 32768;
 
 hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
@@ -109,9 +110,19 @@ hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* ci
   }
   if constexpr (kBlock || kHasBlk) {
     if (kBlock || impl == 1 || impl == 3) {
-      // a batch that leaves SIMDs without a wavefront runs two lanes per instance
-      // (lower latency, twice the lanes) unless one lane was asked for (impl 3);
-      // the workspace has room for either
+      // a batch that leaves SIMDs without a wavefront runs four or two lanes per
+      // instance (lower latency, more lanes) unless one lane was asked for (impl 3);
+      // the workspace has room for any of them
+      if (count <= kFourLaneMax && impl != 3) {
+        const uint32_t blocks4 = (count + 15) / 16;
+        if (trunc)
+          hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, false, 4>), dim3(blocks4), dim3(64), 0, st, ctx, cidx, base,
+                             ex, ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
+        else
+          hipLaunchKernelGGL((k_modexp_blk<kH, kK, false, false, 4>), dim3(blocks4), dim3(64), 0, st, ctx, cidx,
+                             base, ex, ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
+        return hipGetLastError();
+      }
       if (count <= kTwoLaneMax && impl != 3) {
         const uint32_t blocks2 = (count + 31) / 32;
         if (trunc)

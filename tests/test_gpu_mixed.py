@@ -62,9 +62,10 @@ def test_block_kernel_small_and_large_windows(mx, window):
     ctx.close()
 
 
-def test_block_kernel_one_and_two_lanes_per_instance_agree(mx):
-    # batches of at most 32768 instances run two lanes per instance, larger ones one: the same
-    # instances computed both ways (a 33001-instance batch and a 4000-instance slice of it)
+def test_block_kernel_one_two_and_four_lanes_per_instance_agree(mx):
+    # batches of at most 16384 instances run four lanes per instance, up to 32768 two, larger ones
+    # one: the same instances computed all three ways (a 33001-instance batch, a 20001-instance and
+    # a 4001-instance slice of it) and with one lane forced
     bits, n = 1024, 33001
     mods = wl.random_moduli(wl.stream(13, "moduli"), bits, n)
     ctx = mx.Context(mods, bits)
@@ -77,7 +78,11 @@ def test_block_kernel_one_and_two_lanes_per_instance_agree(mx):
     idx = torch.arange(lo, hi, dtype=torch.int32, device=bd.device)
     two = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
                              ctx_idx=idx))
-    assert two == one[lo:hi]
+    assert two == one[lo:hi]  # four lanes per instance
+    lo2 = n - 20001
+    idx2 = torch.arange(lo2, n, dtype=torch.int32, device=bd.device)
+    assert dev_ints(mx.modexp(ctx, bd[lo2:].contiguous(), ed[lo2:].contiguous(), bits, window=3, block=True,
+                              ctx_idx=idx2)) == one[lo2:]  # two lanes per instance
     forced = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
                                 ctx_idx=idx, one_lane=True))  # MX_ONE_LANE: one lane per instance at any size
     assert forced == one[lo:hi]
