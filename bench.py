@@ -21,8 +21,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = "2048-bit modexp/s (truncated vs plain Montgomery), % int-mul peak; p99 latency"
-KERNEL_SOURCES = ("mx_core.hpp", "mx_kernels.hpp", "mx_class.hip")
+METRIC = "2048-bit modexp/s (truncated vs plain Montgomery and CIOS), % int-mul peak; p99 latency"
+KERNEL_SOURCES = ("mx_core.hpp", "mx_kernels.hpp")  # the headline kernel's code (mx_class.hip only launches it)
 SERVE_SLOTS = 2  # serving: execution slots per size class
 
 
@@ -52,6 +52,11 @@ def copy_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": n, "copies": 3}))
+
+
+def progress(msg):
+    """One line on stderr when a measured section ends (the JSON result goes to stdout)."""
+    print("bench.py: %s" % msg, file=sys.stderr, flush=True)
 
 
 def kernel_hash():
@@ -161,8 +166,8 @@ def main():
     # ---- headline: config 2, 65536 x 2048-bit, window 5, truncated ---------
     b2 = Batch(mx, bits, n, 2, dev)
 
-    def step(plain=False, win=w):
-        mx.modexp(b2.ctx, b2.base, b2.exp, bits, window=win, out=b2.out, plain=plain, stream=stream)
+    def step(plain=False, win=w, cios=False):
+        mx.modexp(b2.ctx, b2.base, b2.exp, bits, window=win, out=b2.out, plain=plain, cios=cios, stream=stream)
 
     wall, kms = time_launches(step, a.steps, a.warmup, stream)
     value = n * a.steps / wall
@@ -192,6 +197,13 @@ def main():
     res["plain"] = {"value": vp, "unit": "modexp/s", "kernel_ms": kp,
                     "frac": prod_p * n / (kp * 1e-3) / counts.PEAK_MAD_PER_S}
     res["trunc_speedup"] = value / vp
+    # the word-interleaved multiplication (Algorithm 4, CIOS) on the same inputs
+    wall_c, kms_c = time_launches(lambda: step(cios=True), max(2, a.steps // 2), 1, stream)
+    vc = n * len(kms_c) / wall_c
+    kc = sum(kms_c) / len(kms_c)
+    res["cios"] = {"value": vc, "unit": "modexp/s", "kernel_ms": kc,
+                   "frac": counts.modexp_products(bits, bits, w, cios=True) * n / (kc * 1e-3) / counts.PEAK_MAD_PER_S}
+    res["trunc_vs_cios"] = value / vc
     # the window the library picks for this class (3: the table stays in the last-level cache)
     tuned = {}
     for plain in (False, True):
@@ -202,23 +214,27 @@ def main():
             tuned["frac"] = p3 * n / (sum(k3) / len(k3) * 1e-3) / counts.PEAK_MAD_PER_S
     tuned["trunc_speedup"] = tuned["trunc"] / tuned["plain"]
     res["window3"] = tuned
+    progress("headline, plain, CIOS and window-3 launches done")
     # modmul / modsqr per second on the same moduli (values in [0, 2N))
     A = torch.nn.functional.pad(b2.base, (0, b2.ctx.mont_words - b2.ctx.words))
     B = torch.roll(A, 1, 0).contiguous()
     O = torch.empty_like(A)
     nl = counts.limbs(bits)
-    for op, fn in (("mul", lambda plain: mx.mont_mul(b2.ctx, A, B, out=O, plain=plain, stream=stream)),
-                   ("sqr", lambda plain: mx.mont_sqr(b2.ctx, A, out=O, plain=plain, stream=stream))):
+    for op, fn in (("mul", lambda kw: mx.mont_mul(b2.ctx, A, B, out=O, stream=stream, **kw)),
+                   ("sqr", lambda kw: mx.mont_sqr(b2.ctx, A, out=O, stream=stream, **kw))):
         rates = {}
-        for plain in (False, True):
-            wl_, kk = time_launches(lambda: fn(plain), 20, 3, stream)
-            rates[plain] = n * 20 / wl_
-            if not plain:
-                res["mod%s_per_s" % op] = rates[plain]
+        for r, kw in (("trunc", {}), ("plain", {"plain": True}), ("cios", {"cios": True})):
+            wl_, kk = time_launches(lambda: fn(kw), 20, 3, stream)
+            rates[r] = n * 20 / wl_
+            if r == "trunc":
+                res["mod%s_per_s" % op] = rates[r]
                 res["mod%s_frac" % op] = (counts.op_products(nl, True)[op] * n / (sum(kk) / len(kk) * 1e-3)
                                           / counts.PEAK_MAD_PER_S)
-        res["mod%s_trunc_speedup" % op] = rates[False] / rates[True]
+        res["mod%s_trunc_speedup" % op] = rates["trunc"] / rates["plain"]
+        res["mod%s_cios_per_s" % op] = rates["cios"]
+        res["mod%s_trunc_vs_cios" % op] = rates["trunc"] / rates["cios"]
     b2.ctx.close()
+    progress("modmul / modsqr done")
     del b2
 
     if not a.quick:
@@ -237,12 +253,12 @@ def other_workloads(a, mx, counts, dev, stream):
     # ---- config 1: 8 x 1024-bit ------------------------------------------------
     b1 = Batch(mx, 1024, 8, 1, dev)
     c1 = {}
-    for plain in (False, True):
-        tag = "plain" if plain else "trunc"
-        wl_, k = time_launches(lambda: mx.modexp(b1.ctx, b1.base, b1.exp, 1024, window=5, out=b1.out, plain=plain,
-                                                 stream=stream), 5, 2, stream)
+    for tag, kw in (("trunc", {}), ("plain", {"plain": True}), ("cios", {"cios": True})):
+        wl_, k = time_launches(lambda: mx.modexp(b1.ctx, b1.base, b1.exp, 1024, window=5, out=b1.out, stream=stream,
+                                                 **kw), 5, 2, stream)
         c1["modexp_ms_" + tag] = min(k)
     out["c1_1024x8"] = c1
+    progress("8 x 1024-bit done")
     b1.ctx.close()
     # ---- config 3: 16384 x 4096-bit, schoolbook vs one-level Karatsuba -------------
     b3 = Batch(mx, 4096, 16384, 3, dev)
@@ -259,6 +275,7 @@ def other_workloads(a, mx, counts, dev, stream):
         wl_, _ = time_launches(lambda: mx.mont_mul(b3.ctx, A, A, out=O, block=impl, stream=stream), 5, 1, stream)
         c3["modmul_per_s_" + tag] = b3.n * 5 / wl_
     out["c3_4096x16384"] = c3
+    progress("16384 x 4096-bit done")
     b3.ctx.close()
     del b3
     # ---- config 4: 200k mixed sizes, one persistent launch ------------------------------
@@ -276,6 +293,7 @@ def other_workloads(a, mx, counts, dev, stream):
     out["c4_mixed_200k"] = {"modexp_per_s": 200000 * 2 / wl_, "ms_per_launch": wl_ * 1e3 / 2,
                             "counts": nb, "windows": plan.windows, "jobs": plan.njobs, "persistent_waves": plan.nslots,
                             "frac": work / (sum(k) / len(k) * 1e-3) / counts.PEAK_MAD_PER_S, "hip_graph": True}
+    progress("200k mixed launch done")
     offline = 200000 * 2 / wl_
     plan.close()
     for bb in batches:
@@ -303,6 +321,7 @@ def other_workloads(a, mx, counts, dev, stream):
         ex.close()
         del ex, tr
         torch.cuda.synchronize()
+        progress("serving at %.0f req/s done" % r)
     out["c5_serving"] = {"moduli": 2000, "slots_per_class": SERVE_SLOTS,
                          "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")), "sweep": sweep,
                          "offline_mixed_modexp_per_s": offline}

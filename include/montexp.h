@@ -60,12 +60,18 @@ enum {
   MX_MUL_KARATSUBA = 4, /* block kernels whose product (A*B or A^2) is one-level
                            Karatsuba over half-size block numbers (Section 3):
                            2048 and 4096 bits; same results                  */
-  MX_ONE_LANE = 8      /* exponentiation with the block kernels: one lane per
+  MX_ONE_LANE = 8,     /* exponentiation with the block kernels: one lane per
                           instance even for batches of at most 32768 (which
                           otherwise run four lanes per instance up to 16384
                           and two up to 32768: lower latency, more lanes); for
                           loaded devices where throughput matters more than
                           latency; same results                              */
+  MX_REDC_CIOS = 16    /* word-interleaved Montgomery multiplication (Section
+                          4, Algorithm 4, CIOS): for each limb a_i, Y += a_i B,
+                          q_i = Y_0 N'_0 mod 2^28, Y = (Y + q_i N) / 2^28;
+                          same results.  Register-resident classes (<= 2048
+                          bits) only, else MX_EUNSUPPORTED; with MX_REDC_PLAIN,
+                          MX_EINVAL; not in the mixed launch                 */
 };
 
 /* Montgomery contexts for `count` moduli of size class `bits` (Section 4:
@@ -127,6 +133,7 @@ mx_status modexp_batch_ws(const mont_ctx *ctx, const uint32_t *ctx_idx, const ui
 
 /* Workspace bytes a single launch of n instances needs for this window and flags. */
 mx_status modexp_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t window, uint32_t flags, size_t *bytes);
+
 
 /* ---- mixed sizes in one persistent launch ----------------------------------
  * For callers that hold batches of several size classes at once (not a

@@ -6,6 +6,8 @@ count of the size class, n = ceil((bits + 2) / 28).
   product  (Section 2): mul n^2, sqr n(n+1)/2 (off-diagonal once + diagonal)
   q        (Algorithm 6 step 1 / Algorithm 3 step 1): low half, n(n+1)/2
   q*N      truncated (Theorem 2): n(n+1)/2 + n - 1;  plain (B_fma): n^2
+  CIOS     (Algorithm 4): per limb a_i, n products a_i b_j, one for q_i and n
+           for q_i N_j: 2n^2 + n, for a square too
 Exponentiation (Algorithm 7) with W = ceil(ebits / w) windows runs 2^w - 1
 multiplications for the conversion and the table, (W - 1) w squarings,
 W - 1 multiplications and one final multiplication by 1 (leaving
@@ -29,7 +31,9 @@ def limbs(bits):
     return n
 
 
-def op_products(n, trunc=True):
+def op_products(n, trunc=True, cios=False):
+    if cios:
+        return {"mul": 2 * n * n + n, "sqr": 2 * n * n + n}
     tri = n * (n + 1) // 2
     qn = tri + n - 1 if trunc else n * n
     return {"mul": n * n + tri + qn, "sqr": tri + tri + qn}
@@ -40,9 +44,9 @@ def modexp_schedule(ebits, w):
     return {"mul": (1 << w) - 1 + (nwin - 1) + 1, "sqr": (nwin - 1) * w, "windows": nwin}
 
 
-def modexp_products(bits, ebits, w, trunc=True):
+def modexp_products(bits, ebits, w, trunc=True, cios=False):
     n = limbs(bits)
-    p = op_products(n, trunc)
+    p = op_products(n, trunc, cios)
     s = modexp_schedule(ebits, w)
     return s["mul"] * p["mul"] + s["sqr"] * p["sqr"]
 

@@ -91,6 +91,21 @@ static int impl_of(const mont_ctx* ctx, uint32_t flags) {
   return (flags & MX_ONE_LANE) && ctx->bits > 2048 ? 3 : 0;
 }
 
+// Reduction of the flags (mx::Redc); -1 if MX_REDC_PLAIN and MX_REDC_CIOS are both set.
+static int redc_of(uint32_t flags) {
+  if ((flags & MX_REDC_PLAIN) && (flags & MX_REDC_CIOS)) return -1;
+  return (flags & MX_REDC_CIOS) ? mx::kRedcCios : (flags & MX_REDC_PLAIN) ? mx::kRedcPlain : mx::kRedcTrunc;
+}
+
+// Checks the reduction flags against the kernel family; MX_OK or the failure status.
+static mx_status check_redc(const char* name, const mont_ctx* ctx, int impl, int redc) {
+  if (redc < 0) return fail(MX_EINVAL, "%s: MX_REDC_PLAIN and MX_REDC_CIOS exclude each other", name);
+  if (redc == mx::kRedcCios && (impl != 0 || !ctx->ops->has_cios))
+    return fail(MX_EUNSUPPORTED, "%s: MX_REDC_CIOS is built for the register-resident classes (<= 2048 bits) only",
+                name);
+  return MX_OK;
+}
+
 // Instances per launch so that rows * padded count * 4 bytes fits one descriptor.
 static uint32_t chunk_for(uint32_t rows, uint32_t n) {
   if (rows == 0) return n;
@@ -215,10 +230,12 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!a || !out || (!sqr && !b)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA))
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_REDC_CIOS))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
   const int impl = impl_of(ctx, flags);
   if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
+  const int redc = redc_of(flags);
+  if (mx_status rs = check_redc(name, ctx, impl, redc); rs != MX_OK) return rs;
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
@@ -234,7 +251,7 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   const uint32_t mw = words_for(28 * ctx->limbs);
   for (uint32_t off = 0; off < n; off += chunk) {
     const uint32_t cnt = n - off < chunk ? n - off : chunk;
-    hipError_t e = ctx->ops->mont(impl, !(flags & MX_REDC_PLAIN), sqr, ctx->dev, ctx_idx ? ctx_idx + off : nullptr,
+    hipError_t e = ctx->ops->mont(impl, redc, sqr, ctx->dev, ctx_idx ? ctx_idx + off : nullptr,
                                   a + (size_t)off * mw, b + (size_t)off * mw, out + (size_t)off * mw, cnt,
                                   (uint32_t*)mctx->ws, tstride, (uint32_t)need, ctx_idx ? 0u : off,
                                   (hipStream_t)stream);
@@ -259,10 +276,12 @@ static mx_status modexp_common(const char* name, mont_ctx* ctx, const uint32_t* 
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!base || !out || (exp_bits && !exp)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE))
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_REDC_CIOS))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
   const int impl = impl_of(ctx, flags);
   if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
+  const int redc = redc_of(flags);
+  if (mx_status rs = check_redc(name, ctx, impl, redc); rs != MX_OK) return rs;
   if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   const uint32_t w = window ? window : default_window(ctx->bits);
@@ -293,10 +312,9 @@ static mx_status modexp_common(const char* name, mont_ctx* ctx, const uint32_t* 
     if (ms != MX_OK) return ms;
     ws = ctx->ws;
   }
-  const bool trunc = !(flags & MX_REDC_PLAIN);
   for (uint32_t off = 0; off < n; off += chunk) {
     const uint32_t cnt = n - off < chunk ? n - off : chunk;
-    hipError_t e = ctx->ops->modexp(impl, trunc, ctx->dev, ctx_idx ? ctx_idx + off : nullptr, base + (size_t)off * W,
+    hipError_t e = ctx->ops->modexp(impl, redc, ctx->dev, ctx_idx ? ctx_idx + off : nullptr, base + (size_t)off * W,
                                     exp_bits ? exp + (size_t)off * ewords : exp, exp_bits, ewords, w,
                                     out + (size_t)off * W, cnt, (uint32_t*)ws, tstride, (uint32_t)need,
                                     ctx_idx ? 0u : off, (hipStream_t)stream);

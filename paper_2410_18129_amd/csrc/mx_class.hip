@@ -1,14 +1,52 @@
 // Per-size-class instantiation of the kernels.  Built once per class with
 // -DMX_CLASS_BITS=<bits>; each object exports mx::class_ops_<bits>().
 // Classes up to 2048 bits use the register-resident kernels (mx_kernels.hpp);
-// larger classes use the block-level schoolbook (mx_block.hpp).
+// larger classes use the block-level schoolbook (mx_block.hpp).  The
+// word-interleaved kernels (Algorithm 4) of a register-resident class are
+// built separately, with -DMX_CIOS_UNIT as well, so that they compile in
+// parallel with the rest of the class; that object exports the launchers
+// cios_mont_<bits> and cios_modexp_<bits>.
 #include "mx_block.hpp"
 
 #ifndef MX_CLASS_BITS
 #error "MX_CLASS_BITS must be defined"
 #endif
 
+#define MX_CAT2(a, b) a##b
+#define MX_CAT(a, b) MX_CAT2(a, b)
+
 namespace mx {
+
+#if MX_CLASS_BITS <= 2048
+hipError_t MX_CAT(cios_mont_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
+                                             const uint64_t* b, uint64_t* out, uint32_t count, uint32_t coff,
+                                             hipStream_t st);
+hipError_t MX_CAT(cios_modexp_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
+                                               const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w,
+                                               uint64_t* out, uint32_t count, uint32_t* ws, uint32_t ws_bytes,
+                                               uint32_t coff, hipStream_t st);
+#endif
+
+#ifdef MX_CIOS_UNIT
+static_assert(MX_CLASS_BITS <= 2048, "the word-interleaved kernels exist for the register-resident classes");
+constexpr int kCiosN = limbs_for(MX_CLASS_BITS);
+hipError_t MX_CAT(cios_mont_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
+                                             const uint64_t* b, uint64_t* out, uint32_t count, uint32_t coff,
+                                             hipStream_t st) {
+  hipLaunchKernelGGL((k_mont_cios<kCiosN, words_for(28 * kCiosN)>), dim3((count + 63) / 64), dim3(64), 0, st, ctx,
+                     cidx, a, b, out, count, coff);
+  return hipGetLastError();
+}
+hipError_t MX_CAT(cios_modexp_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
+                                               const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w,
+                                               uint64_t* out, uint32_t count, uint32_t* ws, uint32_t ws_bytes,
+                                               uint32_t coff, hipStream_t st) {
+  hipLaunchKernelGGL((k_modexp_cios<kCiosN, words_for(MX_CLASS_BITS)>), dim3((count + 63) / 64), dim3(64), 0, st,
+                     ctx, cidx, base, ex, ebits, ewords, w, out, count, ws, ws_bytes, coff);
+  return hipGetLastError();
+}
+}  // namespace mx
+#else
 namespace {
 
 constexpr int kBits = MX_CLASS_BITS;
@@ -42,10 +80,11 @@ uint32_t ws_rows_fn(int impl, bool modexp, uint32_t w) {
   return modexp ? (1u << w) * (uint32_t)packed_words(kN) : 0u;  // densely packed table entries
 }
 
-hipError_t mont_fn(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
+hipError_t mont_fn(int impl, int redc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
                    const uint64_t* b, uint64_t* out, uint32_t count, uint32_t* ws, uint32_t tstride,
                    uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
   const uint32_t blocks = (count + 63) / 64;
+  const bool trunc = redc == kRedcTrunc;
   if constexpr (kHasKara) {
     if (impl == 2) {
 #define MX_L(T, S)                                                                                                \
@@ -78,6 +117,10 @@ hipError_t mont_fn(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint
     (void)ws;
     (void)tstride;
     (void)ws_bytes;
+#if MX_CLASS_BITS <= 2048
+    // a square is the product with b = a (the caller passes a twice)
+    if (redc == kRedcCios) return MX_CAT(cios_mont_, MX_CLASS_BITS)(ctx, cidx, a, b, out, count, coff, st);
+#endif
 #define MX_L(T, S) \
   hipLaunchKernelGGL((k_mont<kN, kRW, T, S>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count, coff)
     if (trunc) {
@@ -90,13 +133,14 @@ hipError_t mont_fn(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint
   return hipGetLastError();
 }
 
-hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base, const uint64_t* ex,
+hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base, const uint64_t* ex,
                      uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out, uint32_t count, uint32_t* ws,
                      uint32_t tstride, uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
   // each block works in its own tile region of ws (ws_rows x 64 words); tstride,
   // the launch width padded to 64, only sized ws
   (void)tstride;
   const uint32_t blocks = (count + 63) / 64;
+  const bool trunc = redc == kRedcTrunc;
   if constexpr (kHasKara) {
     if (impl == 2) {
       if (trunc)
@@ -143,6 +187,11 @@ hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* ci
     }
   }
   if constexpr (!kBlock) {
+#if MX_CLASS_BITS <= 2048
+    if (redc == kRedcCios)
+      return MX_CAT(cios_modexp_, MX_CLASS_BITS)(ctx, cidx, base, ex, ebits, ewords, w, out, count, ws, ws_bytes, coff,
+                                                 st);
+#endif
     if (trunc)
       hipLaunchKernelGGL((k_modexp<kN, kW, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits, ewords,
                          w, out, count, ws, ws_bytes, coff);
@@ -153,12 +202,12 @@ hipError_t modexp_fn(int impl, bool trunc, const CtxDev& ctx, const uint32_t* ci
   return hipGetLastError();
 }
 
-const ClassOps kOps = {kBits, kN, kHasBlk || kBlock, kHasKara, ctx_fn, ws_rows_fn, mont_fn, modexp_fn};
+// the word-interleaved kernels (Algorithm 4) exist for the register-resident classes
+const ClassOps kOps = {kBits, kN, kHasBlk || kBlock, kHasKara, !kBlock, ctx_fn, ws_rows_fn, mont_fn, modexp_fn};
 
 }  // namespace
 
-#define MX_CAT2(a, b) a##b
-#define MX_CAT(a, b) MX_CAT2(a, b)
 const ClassOps* MX_CAT(class_ops_, MX_CLASS_BITS)() { return &kOps; }
 
 }  // namespace mx
+#endif  // MX_CIOS_UNIT

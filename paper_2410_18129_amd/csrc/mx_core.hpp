@@ -321,6 +321,75 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
   c[N - 1] = (uint32_t)(carry + t[2 * N - 1]);
 }
 
+// ---- word-interleaved Montgomery multiplication (Section 4, Algorithm 4) --
+//
+// CIOS: for each limb a_i of the first operand, Y += a_i B, then
+// q_i = (Y mod 2^28) N'_0 mod 2^28 and Y = (Y + q_i N) / 2^28, with
+// N'_0 = -N^{-1} mod 2^28.  Y lives in 64-bit column sums y[w] indexed by
+// absolute weight, so the division by 2^28 is a renaming: only column i,
+// divisible by 2^28 once q_i N is added, hands its carry to column i+1.  The
+// q_i are the limbs of q = -AB N^{-1} mod R, so c = (AB + qN) / R exactly,
+// the same integer as the separated reduction.  Column w collects at most
+// 2n products below 2^56 plus a carry below 2^37, within 64 bits for
+// n <= 127.  2n^2 + n multiplications, for a square too: the interleaving
+// leaves no room for the symmetry of Algorithm 2.
+//
+// The outer steps run in groups of P: q_i needs only the products of q_i' N
+// (i' < i) that land in column i, so inside a group each q_i' adds its
+// products with N_0 .. N_{P-1} at once, and one sweep over N_P .. N_{n-1}
+// then adds the rest for the whole group, reading each modulus limb once per
+// group instead of once per step.  Every product is formed once; the result
+// does not depend on P.
+//
+// a_i and the modulus limbs come through the loaders lda / ldm (LDS: the
+// column sums, b and the group's q take the registers); b is in registers.
+// c may alias b: it is written after the last read.
+constexpr int kCiosGroup = 4;
+
+template <int N, int P, typename LoadA, typename LoadM>
+__device__ __forceinline__ void cios_mul(LoadA&& lda, const uint32_t (&b)[N], LoadM&& ldm, uint32_t n0,
+                                         uint32_t (&c)[N]) {
+  static_assert(N >= 2 && N <= 127, "64-bit column sums hold at most 254 products plus a carry");
+  uint64_t y[2 * N];
+  sfor<0, 2 * N>([&](auto W) { y[decltype(W)::value] = 0; });
+  sfor<0, (N + P - 1) / P>([&](auto G) {
+    constexpr int i0 = decltype(G)::value * P;
+    constexpr int pg = (N - i0) < P ? (N - i0) : P;
+    uint32_t q[pg], mlo[pg];
+    sfor<0, pg>([&](auto J) { mlo[decltype(J)::value] = ldm(decltype(J)::value); });
+    sfor<0, pg>([&](auto Q) {
+      constexpr int p = decltype(Q)::value;
+      constexpr int i = i0 + p;
+      const uint32_t ai = lda(i);
+      sfor<0, N>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        y[i + j] += (uint64_t)ai * b[j];
+      });
+      q[p] = ((uint32_t)y[i] * n0) & kLimbMask;
+      sfor<0, pg>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        y[i + j] += (uint64_t)q[p] * mlo[j];
+      });
+      y[i + 1] += y[i] >> kLimbBits;
+    });
+    sfor<pg, N>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      const uint32_t mj = ldm(j);
+      sfor<0, pg>([&](auto Q) {
+        constexpr int p = decltype(Q)::value;
+        y[i0 + p + j] += (uint64_t)q[p] * mj;
+      });
+    });
+  });
+  uint64_t carry = 0;
+  sfor<0, N>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    const uint64_t v = y[N + k] + carry;
+    c[k] = (uint32_t)v & kLimbMask;
+    carry = v >> kLimbBits;
+  });
+}
+
 // ---- block routines for the block-level schoolbook (large size classes) ---
 
 // r = a * b mod 2^(28 H): the low half of the product (Algorithm 6 step 1 on a block).

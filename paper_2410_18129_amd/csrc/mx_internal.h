@@ -23,17 +23,20 @@ struct CtxDev {
 // impl: 0 = the class's default kernels, 1 = block-level schoolbook over
 // 37-limb blocks (available when has_block; the default above 2048 bits),
 // 2 = block kernels with a one-level Karatsuba product (when has_kara).
+// redc: one of Redc below; kRedcCios only with impl 0 and has_cios.
+enum Redc : int { kRedcTrunc = 0, kRedcPlain = 1, kRedcCios = 2 };
 struct ClassOps {
   int bits;
   int limbs;
   bool has_block;
   bool has_kara;
+  bool has_cios;
   hipError_t (*ctx_init)(const uint64_t* mods, const CtxDev& ctx, hipStream_t st);
   uint32_t (*ws_rows)(int impl, bool modexp, uint32_t w);
-  hipError_t (*mont)(int impl, bool trunc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
+  hipError_t (*mont)(int impl, int redc, bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
                      const uint64_t* b, uint64_t* out, uint32_t count, uint32_t* ws, uint32_t tstride,
                      uint32_t ws_bytes, uint32_t coff, hipStream_t st);
-  hipError_t (*modexp)(int impl, bool trunc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
+  hipError_t (*modexp)(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
                        const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out,
                        uint32_t count, uint32_t* ws, uint32_t tstride, uint32_t ws_bytes, uint32_t coff,
                        hipStream_t st);

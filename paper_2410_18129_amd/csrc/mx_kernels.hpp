@@ -146,6 +146,37 @@ __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restr
   if (live) contract<N, RW>(r, out + (size_t)inst * RW);
 }
 
+// out = REDC(a * b) by the word-interleaved multiplication of Algorithm 4
+// (cios_mul); a square is the product with b = a (the method has no squaring
+// of its own).  LDS column of the lane: rows 0 .. N-1 the modulus, rows
+// N .. 2N-1 the first operand; N'_0 is limb 0 of N'.
+template <int N, int RW>
+__global__ void __launch_bounds__(64) k_mont_cios(CtxDev ctx, const uint32_t* __restrict__ cidx,
+                                                  const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                                                  uint64_t* __restrict__ out, uint32_t count, uint32_t coff) {
+  const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
+  const bool live = gid < count;
+  const uint32_t inst = live ? gid : count - 1;
+  uint32_t c = cidx ? cidx[inst] : inst + coff;
+  c = c < ctx.count ? c : 0u;
+  const size_t cs = ctx.stride;
+  const uint32_t lane = threadIdx.x;
+
+  __shared__ uint32_t s_ctx[2 * N * 64];
+  uint32_t x[N], r[N];
+  sfor<0, N>([&](auto I) { x[decltype(I)::value] = ctx.n[(size_t)decltype(I)::value * cs + c]; });
+  sfor<0, N>([&](auto I) { s_ctx[decltype(I)::value * 64 + lane] = x[decltype(I)::value]; });
+  const uint32_t n0 = ctx.np[c];
+  expand<N, RW>(a + (size_t)inst * RW, x);
+  sfor<0, N>([&](auto I) { s_ctx[(N + decltype(I)::value) * 64 + lane] = x[decltype(I)::value]; });
+  // plain reads: the compiler reads each word once and keeps what does not
+  // fit the 256 VGPRs in AGPRs (volatile reads, one per use, spill to scratch)
+  const uint32_t* sm = s_ctx + lane;
+  expand<N, RW>(b + (size_t)inst * RW, x);
+  cios_mul<N, kCiosGroup>([&](int i) { return sm[(N + i) * 64]; }, x, [&](int j) { return sm[j * 64]; }, n0, r);
+  if (live) contract<N, RW>(r, out + (size_t)inst * RW);
+}
+
 // ---- constant-time fixed-window exponentiation (Algorithm 7) --------------
 //
 // Per lane: A~ = REDC(base * R^2); table G[0] = R mod N, G[1] = A~,
@@ -190,7 +221,10 @@ __device__ __forceinline__ void stagger(uint32_t block, uint32_t w) {
 // densely), so that every read of the table scan is a whole 256-byte row and
 // a wavefront's table is one contiguous range of memory.
 // s_ctx: 2 N 64 words of LDS for the lane's N and N'.
-template <int N, int BW, bool TRUNC>
+// CIOS: every Montgomery product is the word-interleaved one of Algorithm 4
+// (cios_mul); s_ctx then holds the modulus (rows 0 .. N-1) and a copy of Y,
+// the first operand of every product (rows N .. 2N-1), and TRUNC is unused.
+template <int N, int BW, bool TRUNC, bool CIOS = false>
 __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
                                             const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                             uint32_t ebits, uint32_t ewords, uint32_t w,
@@ -216,7 +250,15 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
   const uint32_t nent = 1u << w;
   const uint32_t nwin = ebits ? (ebits + w - 1) / w : 1u;
 
-  stage_ctx<N>(s_ctx, cn, cnp, cs, lane);
+  uint32_t n0 = 0;
+  if constexpr (CIOS) {
+    uint32_t v[N];
+    sfor<0, N>([&](auto I) { v[decltype(I)::value] = cn[(size_t)decltype(I)::value * cs]; });
+    sfor<0, N>([&](auto I) { s_ctx[decltype(I)::value * 64 + lane] = v[decltype(I)::value]; });
+    n0 = cnp[0];
+  } else {
+    stage_ctx<N>(s_ctx, cn, cnp, cs, lane);
+  }
   const uint32_t* sm = s_ctx + lane;
 
   uint32_t y[N];
@@ -251,6 +293,11 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
       kind = kMulOne;
     }
 
+    if constexpr (CIOS) {
+      // Y, the first operand of this step's product, goes to the lane's LDS
+      // column before the table scan, so it takes no registers meanwhile
+      if (kind != kLoadSel) sfor<0, N>([&](auto I) { s_ctx[(N + decltype(I)::value) * 64 + lane] = y[decltype(I)::value]; });
+    }
     uint32_t bsrc[N];
     if (kind == kMulSel || kind == kLoadSel) {
       // window bits [win w, win w + w) of the exponent, clipped to ebits
@@ -301,12 +348,19 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
       sfor<0, N>([&](auto I) { bsrc[decltype(I)::value] = decltype(I)::value == 0 ? 1u : 0u; });
     }
 
-    uint32_t t[2 * N];
-    if (kind == kSqr)
-      sqr_sb<N>(y, t);
-    else
-      mul_sb<N>(y, bsrc, t);
-    redc_blk<N, TRUNC>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, y);
+    if constexpr (CIOS) {
+      // one copy of the multiplication code: a squaring multiplies Y by itself
+      if (kind == kSqr) sfor<0, N>([&](auto I) { bsrc[decltype(I)::value] = y[decltype(I)::value]; });
+      cios_mul<N, kCiosGroup>([&](int i) { return sm[(N + i) * 64]; }, bsrc, [&](int j) { return sm[j * 64]; }, n0,
+                              y);
+    } else {
+      uint32_t t[2 * N];
+      if (kind == kSqr)
+        sqr_sb<N>(y, t);
+      else
+        mul_sb<N>(y, bsrc, t);
+      redc_blk<N, TRUNC>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, y);
+    }
     if (store_e >= 0) {
       const uint32_t s0 = (uint32_t)store_e * ent_bytes;
       uint32_t pw[NW];
@@ -336,5 +390,20 @@ __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __res
                             tbytes, coff, tile0, s_ctx);
 }
 
+// As k_modexp with the word-interleaved multiplication (Algorithm 4).
+template <int N, int BW>
+__global__ void __launch_bounds__(64) k_modexp_cios(CtxDev ctx, const uint32_t* __restrict__ cidx,
+                                                    const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
+                                                    uint32_t ebits, uint32_t ewords, uint32_t w,
+                                                    uint64_t* __restrict__ out, uint32_t count,
+                                                    uint32_t* __restrict__ ws, uint32_t ws_bytes, uint32_t coff) {
+  __shared__ uint32_t s_ctx[2 * N * 64];
+  const uint32_t tile0 = blockIdx.x * 64;
+  const uint32_t tbytes = (1u << w) * (uint32_t)packed_words(N) * 256u;
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  stagger<N>(blockIdx.x, w);
+  modexp_tile<N, BW, false, true>(ctx, cidx, base, ex, ebits, ewords, w, out, count,
+                                  ws + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0, s_ctx);
+}
 
 }  // namespace mx

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmontexp.so")
 
 MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EUNSUPPORTED = 0, 1, 2, 3, 4
-MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA, MX_ONE_LANE = 0, 1, 2, 4, 8
+MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA, MX_ONE_LANE, MX_REDC_CIOS = 0, 1, 2, 4, 8, 16
 SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
@@ -175,6 +175,11 @@ def _impl_flags(block):
     return MX_IMPL_BLOCK if block else 0
 
 
+def _redc_flags(plain, cios):
+    """plain: full q*N product (Algorithm 3); cios: word-interleaved (Algorithm 4); else truncated."""
+    return (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | (MX_REDC_CIOS if cios else 0)
+
+
 def _check_rows(name, t, n, words):
     """Shape/dtype/device checks that keep every kernel access inside the buffers."""
     import torch
@@ -194,7 +199,7 @@ def _check_idx(ctx_idx, n, ctx):
         raise ValueError("ctx_idx: expected int32 device tensor [%d]" % n)
 
 
-def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=False):
+def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=False, cios=False):
     """REDC(a*b) per instance; a, b: int64 device tensors [n, mont_words]."""
     n = a.shape[0]
     if out is None:
@@ -203,13 +208,13 @@ def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=
     for nm, t in (("a", a), ("b", b), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block)
+    flags = _redc_flags(plain, cios) | _impl_flags(block)
     _check(lib().mont_mul_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(b), _ptr(out), n, flags,
                                 _stream_ptr(stream)))
     return out
 
 
-def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=False):
+def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=False, cios=False):
     """REDC(a^2) per instance; a: int64 device tensor [n, mont_words]."""
     n = a.shape[0]
     if out is None:
@@ -218,16 +223,17 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=Fal
     for nm, t in (("a", a), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block)
+    flags = _redc_flags(plain, cios) | _impl_flags(block)
     _check(lib().mont_sqr_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(out), n, flags, _stream_ptr(stream)))
     return out
 
 
 def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None, block=False,
-           one_lane=False):
+           one_lane=False, cios=False):
     """base^exp mod N per instance; base: int64 [n, words], exp: int64 [n, ceil(exp_bits/64)].
 
-    one_lane: block kernels keep one lane per instance for small batches too (MX_ONE_LANE)."""
+    one_lane: block kernels keep one lane per instance for small batches too (MX_ONE_LANE).
+    cios: word-interleaved Montgomery products (Algorithm 4, MX_REDC_CIOS; classes up to 2048 bits)."""
     n = base.shape[0]
     if out is None:
         import torch
@@ -237,7 +243,7 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
     if exp_bits:
         _check_rows("exp", exp, n, words_for(exp_bits))
     _check_idx(ctx_idx, n, ctx)
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0)
+    flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0)
     _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,
                               window, _ptr(out), n, flags, _stream_ptr(stream)))
     return out
@@ -308,7 +314,7 @@ def modexp_ws_bytes(ctx, n, window=0, block=False):
 
 
 def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, plain=False, stream=None,
-              block=False, n=None, one_lane=False):
+              block=False, n=None, one_lane=False, cios=False):
     """modexp with a caller-owned workspace tensor (uint8/any dtype, device); n rows of base/exp used."""
     n = base.shape[0] if n is None else n
     if out is None:
@@ -327,7 +333,7 @@ def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, pl
         raise ValueError("n exceeds the context count (pass ctx_idx)")
     if not ws.is_cuda or not ws.is_contiguous():
         raise ValueError("ws: expected a contiguous device tensor")
-    flags = (MX_REDC_PLAIN if plain else MX_REDC_TRUNC) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0)
+    flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0)
     _check(lib().modexp_batch_ws(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None,
                                  exp_bits, window, _ptr(out), n, flags, _ptr(ws), ws.numel() * ws.element_size(),
                                  _stream_ptr(stream)))

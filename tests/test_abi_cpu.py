@@ -50,3 +50,26 @@ def test_host_side_argument_errors_without_gpu():
     assert L.mont_ctx_init(ctypes.byref(h), odd.ctypes.data_as(ctypes.c_void_p), 64, 0, None) == mx.MX_EINVAL
     assert L.mont_mul_batch(None, None, None, None, None, 1, 0, None) == mx.MX_EINVAL
     assert L.modexp_batch(None, None, None, None, 8, 5, None, 1, 0, None) == mx.MX_EINVAL
+
+
+def test_header_constants_match_the_binding():
+    """Status codes and flags have the same values in include/montexp.h and the Python binding."""
+    from paper_2410_18129_amd import montexp
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    vals = dict((k, int(v)) for k, v in re.findall(r"\b(MX_[A-Z_]+)\s*=\s*(\d+)", src))
+    for name in ("MX_OK", "MX_EINVAL", "MX_ENOMEM", "MX_EDEVICE", "MX_EUNSUPPORTED", "MX_REDC_TRUNC",
+                 "MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS"):
+        assert vals[name] == getattr(montexp, name), name
+    flags = [vals[k] for k in ("MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS")]
+    assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)
+
+
+def test_work_counts_match_the_model():
+    """The bench's product counts per operation equal the oracle model's (all three reductions)."""
+    from oracle import montred_model as m
+    from paper_2410_18129_amd import counts
+    for n in (3, 37, 74):
+        c = m.counts(n)
+        assert counts.op_products(n, trunc=True) == {"mul": c["mul_trunc"], "sqr": c["sqr_trunc"]}
+        assert counts.op_products(n, trunc=False) == {"mul": c["mul_plain"], "sqr": c["sqr_plain"]}
+        assert counts.op_products(n, cios=True) == {"mul": c["mul_cios"], "sqr": c["sqr_cios"]}

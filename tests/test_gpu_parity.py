@@ -31,6 +31,15 @@ def _moduli(bits, count, k=1):
     return wl.random_moduli(wl.stream(k, "moduli"), bits, count)
 
 
+def _redcs(bits):
+    """Reductions built for a class: truncated (Algorithm 6), plain (Algorithm 3) and, up to 2048 bits,
+    the word-interleaved CIOS (Algorithm 4); as keyword arguments of the binding."""
+    r = {"trunc": {}, "plain": {"plain": True}}
+    if bits <= 2048:
+        r["cios"] = {"cios": True}
+    return r
+
+
 @pytest.mark.parametrize("bits", CLASSES)
 def test_context_constants(mx, bits):
     mods = _moduli(bits, 70)  # 70: one full wavefront and a ragged tail
@@ -59,19 +68,21 @@ def test_mont_mul_sqr_random(mx, bits, count):
     B = wl.random_below(g, mods, bits, scale=2)
     a, b = ints_dev(A, ctx.mont_words), ints_dev(B, ctx.mont_words)
     outs = {}
-    for plain in (False, True):
-        outs[("mul", plain)] = dev_ints(mx.mont_mul(ctx, a, b, plain=plain))
-        outs[("sqr", plain)] = dev_ints(mx.mont_sqr(ctx, a, plain=plain))
+    redcs = _redcs(bits)
+    for r, kw in redcs.items():
+        outs[("mul", r)] = dev_ints(mx.mont_mul(ctx, a, b, **kw))
+        outs[("sqr", r)] = dev_ints(mx.mont_sqr(ctx, a, **kw))
     idx = range(count) if count <= 8 or bits <= 512 else [0, 1, 31, 63, 64, count - 1]
     for i in idx:
         exp_mul = oracle.montmul(A[i], B[i], Ns[i], rb)
         exp_sqr = oracle.montmul(A[i], A[i], Ns[i], rb)
-        for plain in (False, True):
-            assert outs[("mul", plain)][i] == exp_mul, (i, plain)
-            assert outs[("sqr", plain)][i] == exp_sqr, (i, plain)
-    # truncated and plain reductions agree bit for bit on every instance (Theorem 1)
-    assert outs[("mul", False)] == outs[("mul", True)]
-    assert outs[("sqr", False)] == outs[("sqr", True)]
+        for r in redcs:
+            assert outs[("mul", r)][i] == exp_mul, (i, r)
+            assert outs[("sqr", r)][i] == exp_sqr, (i, r)
+    # every reduction gives the same integer on every instance (Theorem 1; q in [0, R) is unique)
+    for r in redcs:
+        assert outs[("mul", r)] == outs[("mul", "trunc")], r
+        assert outs[("sqr", r)] == outs[("sqr", "trunc")], r
     ctx.close()
 
 
@@ -90,12 +101,12 @@ def test_mont_mul_adversarial(mx, bits):
     rb = ctx.r_bits
     a = ints_dev([p[1] for p in pairs], ctx.mont_words)
     b = ints_dev([p[2] for p in pairs], ctx.mont_words)
-    for plain in (False, True):
-        got = dev_ints(mx.mont_mul(ctx, a, b, plain=plain))
-        gsq = dev_ints(mx.mont_sqr(ctx, a, plain=plain))
+    for r, kw in _redcs(bits).items():
+        got = dev_ints(mx.mont_mul(ctx, a, b, **kw))
+        gsq = dev_ints(mx.mont_sqr(ctx, a, **kw))
         for i, (N, x, y) in enumerate(pairs):
-            assert got[i] == oracle.montmul(x, y, N, rb), (i, plain)
-            assert gsq[i] == oracle.montmul(x, x, N, rb), (i, plain)
+            assert got[i] == oracle.montmul(x, y, N, rb), (i, r)
+            assert gsq[i] == oracle.montmul(x, x, N, rb), (i, r)
     ctx.close()
 
 
@@ -130,12 +141,13 @@ def test_modexp_random(mx, bits, window):
     bd = ints_dev(base, ctx.words)
     ed = ints_dev(exps, ctx.words)
     res = {}
-    for plain in (False, True):
-        res[plain] = dev_ints(mx.modexp(ctx, bd, ed, bits, window=window, plain=plain))
-    assert res[False] == res[True]
+    for r, kw in _redcs(bits).items():
+        res[r] = dev_ints(mx.modexp(ctx, bd, ed, bits, window=window, **kw))
+    for r in res:
+        assert res[r] == res["trunc"], r
     check = range(count) if bits <= 1024 else range(3 if bits <= 2048 else 1)
     for i in check:
-        assert res[False][i] == oracle.modexp(base[i], exps[i], Ns[i], bits), i
+        assert res["trunc"][i] == oracle.modexp(base[i], exps[i], Ns[i], bits), i
     ctx.close()
 
 
@@ -154,12 +166,12 @@ def test_modexp_brute_force_64bit(mx):
             Ns.append(N), B.append(a), E.append(rng.getrandbits(64))
     ctx = mx.Context(wl.ints_to_words(Ns, 1), bits)
     bd, ed = ints_dev(B, 1), ints_dev(E, 1)
-    for w in (1, 2, 4, 5, 8):
-        got = dev_ints(mx.modexp(ctx, bd, ed, 64, window=w))
+    for w, kw in ((1, {}), (2, {}), (4, {}), (5, {}), (8, {}), (1, {"cios": True}), (5, {"cios": True})):
+        got = dev_ints(mx.modexp(ctx, bd, ed, 64, window=w, **kw))
         for i in range(len(Ns)):
             if i % 97 == 0:
-                assert got[i] == oracle.modexp(B[i], E[i], Ns[i], 64), (i, w)
-            assert got[i] == pow(B[i], E[i], Ns[i]), (i, w)
+                assert got[i] == oracle.modexp(B[i], E[i], Ns[i], 64), (i, w, kw)
+            assert got[i] == pow(B[i], E[i], Ns[i]), (i, w, kw)
     ctx.close()
 
 
@@ -232,4 +244,25 @@ def test_errors_and_noops(mx):
     assert ei.value.status == mx.MX_EINVAL
     with pytest.raises(ValueError):
         mx.modexp(ctx, one, one, 65)  # exponent tensor narrower than exp_bits
+    # MX_REDC_PLAIN and MX_REDC_CIOS exclude each other
+    with pytest.raises(mx.MontError) as ei:
+        mx.mont_mul(ctx, a[:1], a[:1], plain=True, cios=True)
+    assert ei.value.status == mx.MX_EINVAL
+    with pytest.raises(mx.MontError) as ei:
+        mx.modexp(ctx, one, one, 8, plain=True, cios=True)
+    assert ei.value.status == mx.MX_EINVAL
     ctx.close()
+    # CIOS exists for the register-resident kernels only: not for the block kernels or above 2048 bits
+    for bits, block in ((2048, True), (3072, False)):
+        m = _moduli(bits, 1, k=8)
+        c = mx.Context(m, bits)
+        x = torch.zeros((1, c.mont_words), dtype=torch.int64, device="cuda")
+        with pytest.raises(mx.MontError) as ei:
+            mx.mont_sqr(c, x, cios=True, block=block)
+        assert ei.value.status == mx.MX_EUNSUPPORTED
+        xb = torch.zeros((1, c.words), dtype=torch.int64, device="cuda")
+        e1 = torch.zeros((1, 1), dtype=torch.int64, device="cuda")
+        with pytest.raises(mx.MontError) as ei:
+            mx.modexp(c, xb, e1, 64, cios=True, block=block)
+        assert ei.value.status == mx.MX_EUNSUPPORTED
+        c.close()
