@@ -239,11 +239,51 @@ def main():
 
     if not a.quick:
         res["workloads"] = other_workloads(a, mx, counts, dev, stream)
+        crt = res["workloads"]["rsa2048_crt"]
+        # an RSA-2048 private-key operation without the CRT is one 2048-bit exponentiation (window 3 above)
+        crt["vs_direct_2048_w3"] = crt["ops_per_s_trunc"] / res["window3"]["trunc"]
     if not a.no_cpu:
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         cores = max(1, min(cores, 16))
         res["cpu_baseline"] = cpu_baseline(bits, a.cpu_sample or 2 * cores, cores)
     print(json.dumps(res), flush=True)
+
+
+def rsa_crt_workload(mx, counts, dev, stream, nr=65536):
+    """RSA-2048 private-key operations by the CRT (two 1024-bit exponentiations and Garner's recombination
+    per operation) over 32 seeded keys, ciphertexts uniform below each key's modulus."""
+    import numpy as np
+    import torch
+    from paper_2410_18129_amd import workload as wl
+    keys = wl.rsa_keys(wl.load_primes(1024))
+    g = wl.stream(10, "misc")
+    key_of = g.integers(0, len(keys), size=nr)
+    cs = wl.rsa_messages(g, keys, key_of)
+    ctx_p = mx.Context(wl.ints_to_words([k["p"] for k in keys], 16), 1024)
+    ctx_q = mx.Context(wl.ints_to_words([k["q"] for k in keys], 16), 1024)
+
+    def dev_words(vals, words):
+        return torch.from_numpy(wl.ints_to_words(vals, words).view(np.int64)).to(dev)
+
+    c = dev_words(cs, 32)
+    dp = dev_words([keys[k]["dp"] for k in key_of], 16)
+    dq = dev_words([keys[k]["dq"] for k in key_of], 16)
+    qi = dev_words([keys[k]["qinv"] for k in key_of], 16)
+    kidx = torch.from_numpy(key_of.astype(np.int32)).to(dev)
+    o = torch.empty_like(c)
+    res = {"instances": nr, "keys": len(keys), "window": 3}
+    for tag, kw in (("trunc", {}), ("plain", {"plain": True})):
+        wl_, k = time_launches(lambda: mx.rsa_crt(ctx_p, ctx_q, c, dp, dq, qi, window=3, out=o, key_idx=kidx,
+                                                  stream=stream, **kw), 3, 1, stream)
+        res["ops_per_s_" + tag] = nr * 3 / wl_
+        res["ms_per_batch_" + tag] = sum(k) / len(k)
+    # work: two 1024-bit exponentiations with 1024-bit exponents per operation (the CRT steps are O(n^2))
+    res["frac"] = (2 * counts.modexp_products(1024, 1024, 3) * nr / (res["ms_per_batch_trunc"] * 1e-3)
+                   / counts.PEAK_MAD_PER_S)
+    res["trunc_speedup"] = res["ops_per_s_trunc"] / res["ops_per_s_plain"]
+    ctx_p.close()
+    ctx_q.close()
+    return res
 
 
 def other_workloads(a, mx, counts, dev, stream):
@@ -276,6 +316,8 @@ def other_workloads(a, mx, counts, dev, stream):
         c3["modmul_per_s_" + tag] = b3.n * 5 / wl_
     out["c3_4096x16384"] = c3
     progress("16384 x 4096-bit done")
+    out["rsa2048_crt"] = rsa_crt_workload(mx, counts, dev, stream)
+    progress("CRT-RSA done")
     b3.ctx.close()
     del b3
     # ---- config 4: 200k mixed sizes, one persistent launch ------------------------------

@@ -66,12 +66,17 @@ enum {
                           and two up to 32768: lower latency, more lanes); for
                           loaded devices where throughput matters more than
                           latency; same results                              */
-  MX_REDC_CIOS = 16    /* word-interleaved Montgomery multiplication (Section
+  MX_REDC_CIOS = 16,   /* word-interleaved Montgomery multiplication (Section
                           4, Algorithm 4, CIOS): for each limb a_i, Y += a_i B,
                           q_i = Y_0 N'_0 mod 2^28, Y = (Y + q_i N) / 2^28;
                           same results.  Register-resident classes (<= 2048
                           bits) only, else MX_EUNSUPPORTED; with MX_REDC_PLAIN,
                           MX_EINVAL; not in the mixed launch                 */
+  MX_TWO_LANES = 32    /* exponentiation with the block kernels: at most two
+                          lanes per instance (batches of at most 16384 would
+                          otherwise run four); a middle ground between latency
+                          and throughput for a moderately loaded device; with
+                          MX_ONE_LANE, MX_EINVAL; same results               */
 };
 
 /* Montgomery contexts for `count` moduli of size class `bits` (Section 4:
@@ -134,6 +139,28 @@ mx_status modexp_batch_ws(const mont_ctx *ctx, const uint32_t *ctx_idx, const ui
 /* Workspace bytes a single launch of n instances needs for this window and flags. */
 mx_status modexp_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t window, uint32_t flags, size_t *bytes);
 
+/* ---- RSA private-key operations by the Chinese remainder theorem -----------
+ * The application the paper's batched exponentiation is built for (Section
+ * 1): out[i] = c[i]^d mod p q for a key given as dp = d mod (p-1),
+ * dq = d mod (q-1) and qinv = q^{-1} mod p.  Computed as
+ *   m1 = (c mod p)^dp mod p,  m2 = (c mod q)^dq mod q   (modexp_batch),
+ *   h = qinv (m1 - m2) mod p,  out = m2 + h q            (Garner),
+ * with c mod p = REDC(REDC(c) R^2 mod p) and h by one Montgomery product.
+ * ctx_p, ctx_q: contexts of the primes, one size class (1024 bits for
+ * RSA-2048, 2048 bits for RSA-4096, else MX_EUNSUPPORTED); key k is context k
+ * of each.  Each prime has exactly `bits` bits (top bit set) and p != q;
+ * otherwise the values are unspecified.  key_idx (device, n entries) picks
+ * each instance's key; NULL means instance i uses key i.  c: 2 W words per
+ * instance (W = bits/64), c < p q; dp, dq, qinv: W words each, dp < p, dq < q,
+ * qinv < p; the exponents have exp_bits = bits.  out: 2 W words per
+ * instance, canonical (< p q).  window and flags (MX_REDC_PLAIN or
+ * MX_REDC_CIOS) apply to the two exponentiations.  out may alias c but not
+ * dp, dq or qinv.  The two intermediates (n W words each) live in a buffer
+ * owned by ctx_p that grows on demand (a growth allocates device memory), next
+ * to the exponentiation workspaces of both contexts. */
+mx_status rsa_crt_batch(const mont_ctx *ctx_p, const mont_ctx *ctx_q, const uint32_t *key_idx, const uint64_t *c,
+                        const uint64_t *dp, const uint64_t *dq, const uint64_t *qinv, uint32_t window,
+                        uint64_t *out, uint32_t n, uint32_t flags, void *stream);
 
 /* ---- mixed sizes in one persistent launch ----------------------------------
  * For callers that hold batches of several size classes at once (not a

@@ -17,6 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmontexp.so")
 CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 CIOS_CLASSES = tuple(c for c in CLASSES if c <= 2048)  # register-resident classes
+CRT_CLASSES = (1024, 2048)  # prime classes of the CRT-RSA operation (RSA-2048, RSA-4096)
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # hipcc flags: packed FP32 ops stay off (the kernels are integer-only anyway)
@@ -48,13 +49,16 @@ def build(jobs=None, only=None, verbose=True):
             units.append(("cios_%d" % b, [HIPCC] + FLAGS + ["-DMX_CLASS_BITS=%d" % b, "-DMX_CIOS_UNIT", "-c",
                                                           os.path.join(CSRC, "mx_class.hip"),
                                                           "-o", os.path.join(BUILD, "mx_cios_%d.o" % b)]))
+    for b in CRT_CLASSES:
+        units.append(("crt_%d" % b, [HIPCC] + FLAGS + ["-DMX_CLASS_BITS=%d" % b, "-c", os.path.join(CSRC, "mx_crt.hip"),
+                                                     "-o", os.path.join(BUILD, "mx_crt_%d.o" % b)]))
     # the issue-rate probe: a standalone program that measures the ALU roofline's issue rates
     units.append(("issue_rate", [HIPCC] + FLAGS + ["-o", os.path.join(HERE, "issue_rate"),
                                                   os.path.join(CSRC, "issue_rate.hip")]))
     jobs = jobs or min(len(units), max(1, os.cpu_count() or 1))
     t0 = time.time()
     # largest classes first so they overlap with the small ones
-    units.sort(key=lambda u: -int(u[0].split("_")[1]) if u[0].startswith(("class_", "cios_")) else
+    units.sort(key=lambda u: -int(u[0].split("_")[1]) if u[0].startswith(("class_", "cios_", "crt_")) else
                (-4096 if u[0] == "mx_mixed" else 0))
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = {ex.submit(_run, cmd): name for name, cmd in units}
@@ -64,7 +68,8 @@ def build(jobs=None, only=None, verbose=True):
                 print("  built %-10s %6.1fs" % (futs[f], dt), flush=True)
     objs = ([os.path.join(BUILD, "mx_abi.o"), os.path.join(BUILD, "mx_mixed.o")] +
             [os.path.join(BUILD, "mx_class_%d.o" % b) for b in CLASSES] +
-            [os.path.join(BUILD, "mx_cios_%d.o" % b) for b in CLASSES if b in CIOS_CLASSES])
+            [os.path.join(BUILD, "mx_cios_%d.o" % b) for b in CLASSES if b in CIOS_CLASSES] +
+            [os.path.join(BUILD, "mx_crt_%d.o" % b) for b in CRT_CLASSES])
     missing = [o for o in objs if not os.path.exists(o)]
     if missing:
         raise RuntimeError("missing objects (build the other classes first): %s" % missing)

@@ -12,6 +12,19 @@
 #include "mx_internal.h"
 #include "mx_ctx.h"
 
+namespace mx {
+// CRT-RSA steps around the two half-size exponentiations (mx_crt.hip, one object per prime class)
+#define MX_DECL_CRT(B)                                                                                                \
+  hipError_t crt_reduce_##B(const CtxDev& ctxp, const CtxDev& ctxq, const uint32_t* kidx, const uint64_t* c,         \
+                            uint64_t* cp, uint64_t* cq, uint32_t count, uint32_t coff, hipStream_t st);             \
+  hipError_t crt_garner_##B(const CtxDev& ctxp, const CtxDev& ctxq, const uint32_t* kidx, const uint64_t* m1,       \
+                            const uint64_t* m2, const uint64_t* qinv, uint64_t* out, uint32_t count, uint32_t coff, \
+                            hipStream_t st);
+MX_DECL_CRT(1024)
+MX_DECL_CRT(2048)
+#undef MX_DECL_CRT
+}  // namespace mx
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -84,11 +97,13 @@ static mx_status ensure_ws(mont_ctx* ctx, size_t need, const char* name) {
 }
 
 // Kernel family for the flags: 0 register-resident, 1 block, 2 block + Karatsuba, 3 block with one
-// lane per instance whatever the batch size (MX_ONE_LANE); -1 if not built.
+// lane per instance whatever the batch size (MX_ONE_LANE), 4 block with at most two lanes per
+// instance (MX_TWO_LANES); -1 if not built.
 static int impl_of(const mont_ctx* ctx, uint32_t flags) {
   if (flags & MX_MUL_KARATSUBA) return ctx->ops->has_kara ? 2 : -1;
-  if (flags & MX_IMPL_BLOCK) return ctx->ops->has_block ? ((flags & MX_ONE_LANE) ? 3 : 1) : -1;
-  return (flags & MX_ONE_LANE) && ctx->bits > 2048 ? 3 : 0;
+  const int blk = (flags & MX_ONE_LANE) ? 3 : (flags & MX_TWO_LANES) ? 4 : 1;
+  if (flags & MX_IMPL_BLOCK) return ctx->ops->has_block ? blk : -1;
+  return ctx->bits > 2048 && blk != 1 ? blk : 0;
 }
 
 // Reduction of the flags (mx::Redc); -1 if MX_REDC_PLAIN and MX_REDC_CIOS are both set.
@@ -220,6 +235,7 @@ mx_status mont_ctx_export(const mont_ctx* ctx, uint32_t idx, uint64_t* nprime_ho
 void mont_ctx_destroy(mont_ctx* ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
+  if (ctx->crt) (void)hipFree(ctx->crt);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->mem) (void)hipFree(ctx->mem);
   delete ctx;
@@ -276,8 +292,11 @@ static mx_status modexp_common(const char* name, mont_ctx* ctx, const uint32_t* 
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!base || !out || (exp_bits && !exp)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_REDC_CIOS))
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_REDC_CIOS |
+                          MX_TWO_LANES))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
+  if ((flags & MX_ONE_LANE) && (flags & MX_TWO_LANES))
+    return fail(MX_EINVAL, "%s: MX_ONE_LANE and MX_TWO_LANES exclude each other", name);
   const int impl = impl_of(ctx, flags);
   if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
   const int redc = redc_of(flags);
@@ -335,6 +354,58 @@ mx_status modexp_batch_ws(const mont_ctx* ctx, const uint32_t* ctx_idx, const ui
   if (!ws) return fail(MX_EINVAL, "modexp_batch_ws: workspace is NULL");
   return modexp_common("modexp_batch_ws", const_cast<mont_ctx*>(ctx), ctx_idx, base, exp, exp_bits, window, out, n,
                        flags, ws, ws_bytes, stream);
+}
+
+mx_status rsa_crt_batch(const mont_ctx* ctx_p, const mont_ctx* ctx_q, const uint32_t* key_idx, const uint64_t* c,
+                        const uint64_t* dp, const uint64_t* dq, const uint64_t* qinv, uint32_t window, uint64_t* out,
+                        uint32_t n, uint32_t flags, void* stream) {
+  const char* name = "rsa_crt_batch";
+  if (!ctx_p || !ctx_q) return fail(MX_EINVAL, "%s: ctx is NULL", name);
+  if (ctx_p->bits != ctx_q->bits) return fail(MX_EINVAL, "%s: p and q contexts of different classes", name);
+  if (ctx_p->device != ctx_q->device) return fail(MX_EINVAL, "%s: contexts on different devices", name);
+  const uint32_t bits = ctx_p->bits;
+  if (bits != 1024 && bits != 2048)
+    return fail(MX_EUNSUPPORTED, "%s: %u-bit primes (1024 and 2048 are built)", name, bits);
+  if (n == 0) return MX_OK;
+  if (!c || !dp || !dq || !qinv || !out) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_REDC_CIOS)) return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
+  if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
+  const uint32_t cnt_min = ctx_p->count < ctx_q->count ? ctx_p->count : ctx_q->count;
+  if (!key_idx && n > cnt_min) return fail(MX_EINVAL, "%s: n=%u exceeds the key count %u", name, n, cnt_min);
+  if (redc_of(flags) < 0) return fail(MX_EINVAL, "%s: MX_REDC_PLAIN and MX_REDC_CIOS exclude each other", name);
+  DeviceGuard g(ctx_p->device);
+  if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
+  mont_ctx* cp = const_cast<mont_ctx*>(ctx_p);
+  mont_ctx* cq = const_cast<mont_ctx*>(ctx_q);
+  const uint32_t W = words_for(bits);
+  const size_t need = (size_t)n * 2 * W * sizeof(uint64_t);
+  std::lock_guard<std::mutex> lk(cp->crt_mu);
+  if (cp->crt_bytes < need) {
+    // the old buffer may still be read by queued work: drain before freeing
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return dev_fail(e, name);
+    if (cp->crt) (void)hipFree(cp->crt);
+    cp->crt = nullptr;
+    cp->crt_bytes = 0;
+    e = hipMalloc(&cp->crt, need);
+    if (e != hipSuccess) return dev_fail(e, name);
+    cp->crt_bytes = need;
+  }
+  uint64_t* xp = (uint64_t*)cp->crt;  // c mod p, then m1
+  uint64_t* xq = xp + (size_t)n * W;   // c mod q, then m2
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = bits == 1024 ? mx::crt_reduce_1024(cp->dev, cq->dev, key_idx, c, xp, xq, n, 0, st)
+                              : mx::crt_reduce_2048(cp->dev, cq->dev, key_idx, c, xp, xq, n, 0, st);
+  if (e != hipSuccess) return dev_fail(e, name);
+  // the two half-size exponentiations, in place (modexp_batch's output may alias its base)
+  mx_status ms = modexp_common(name, cp, key_idx, xp, dp, bits, window, xp, n, flags, nullptr, 0, stream);
+  if (ms != MX_OK) return ms;
+  ms = modexp_common(name, cq, key_idx, xq, dq, bits, window, xq, n, flags, nullptr, 0, stream);
+  if (ms != MX_OK) return ms;
+  e = bits == 1024 ? mx::crt_garner_1024(cp->dev, cq->dev, key_idx, xp, xq, qinv, out, n, 0, st)
+                   : mx::crt_garner_2048(cp->dev, cq->dev, key_idx, xp, xq, qinv, out, n, 0, st);
+  if (e != hipSuccess) return dev_fail(e, name);
+  return MX_OK;
 }
 
 mx_status modexp_ws_bytes(const mont_ctx* ctx, uint32_t n, uint32_t window, uint32_t flags, size_t* bytes) {

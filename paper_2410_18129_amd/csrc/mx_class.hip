@@ -74,7 +74,8 @@ hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
 // per-lane workspace words: block classes keep Y, B, T, Q, S (and the table)
 // in memory; register-resident classes need only the exponentiation table
 uint32_t ws_rows_fn(int impl, bool modexp, uint32_t w) {
-  // impl: 0 register-resident, 1 block, 2 block + Karatsuba, 3 block with one lane per instance
+  // impl: 0 register-resident, 1 block, 2 block + Karatsuba, 3 block with one lane per instance,
+  // 4 block with at most two lanes per instance
   if (kBlock || (kHasBlk && impl >= 1)) return modexp ? BlkLayout<kH, kK>::rows(w) : BlkLayout<kH, kK>::G;
   (void)impl;
   return modexp ? (1u << w) * (uint32_t)packed_words(kN) : 0u;  // densely packed table entries
@@ -153,11 +154,11 @@ hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx
     }
   }
   if constexpr (kBlock || kHasBlk) {
-    if (kBlock || impl == 1 || impl == 3) {
+    if (kBlock || impl == 1 || impl == 3 || impl == 4) {
       // a batch that leaves SIMDs without a wavefront runs four or two lanes per
-      // instance (lower latency, more lanes) unless one lane was asked for (impl 3);
-      // the workspace has room for any of them
-      if (count <= kFourLaneMax && impl != 3) {
+      // instance (lower latency, more lanes) unless one lane (impl 3) or at most two
+      // (impl 4) were asked for; the workspace has room for any of them
+      if (count <= kFourLaneMax && impl != 3 && impl != 4) {
         const uint32_t blocks4 = (count + 15) / 16;
         if (trunc)
           hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, false, 4>), dim3(blocks4), dim3(64), 0, st, ctx, cidx, base,

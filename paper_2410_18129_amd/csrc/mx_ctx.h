@@ -24,5 +24,10 @@ struct mont_ctx {
   std::mutex ws_mu;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // the two half-size intermediates of rsa_crt_batch when this is the context
+  // of the first primes (grow-only; guarded by crt_mu, which is taken before ws_mu)
+  std::mutex crt_mu;
+  void* crt = nullptr;
+  size_t crt_bytes = 0;
 };
 

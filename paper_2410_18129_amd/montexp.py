@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmontexp.so")
 
 MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EUNSUPPORTED = 0, 1, 2, 3, 4
-MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA, MX_ONE_LANE, MX_REDC_CIOS = 0, 1, 2, 4, 8, 16
+MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA, MX_ONE_LANE, MX_REDC_CIOS, MX_TWO_LANES = \
+    0, 1, 2, 4, 8, 16, 32
 SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
@@ -33,6 +34,7 @@ _SIGS = {
     "modexp_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P]),
     "modexp_batch_ws": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P, ctypes.c_size_t, _P]),
     "modexp_ws_bytes": (ctypes.c_int, [_P, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_size_t)]),
+    "rsa_crt_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _U32, _P, _U32, _U32, _P]),
     "mx_mixed_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), _P, _U32]),
     "mx_mixed_plan_launch": (ctypes.c_int, [_P, _P]),
     "mx_mixed_plan_launch_graph": (ctypes.c_int, [_P, _P]),
@@ -229,10 +231,11 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=Fal
 
 
 def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None, block=False,
-           one_lane=False, cios=False):
+           one_lane=False, cios=False, two_lanes=False):
     """base^exp mod N per instance; base: int64 [n, words], exp: int64 [n, ceil(exp_bits/64)].
 
-    one_lane: block kernels keep one lane per instance for small batches too (MX_ONE_LANE).
+    one_lane: block kernels keep one lane per instance for small batches too (MX_ONE_LANE);
+    two_lanes: at most two lanes per instance (MX_TWO_LANES).
     cios: word-interleaved Montgomery products (Algorithm 4, MX_REDC_CIOS; classes up to 2048 bits)."""
     n = base.shape[0]
     if out is None:
@@ -243,7 +246,8 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
     if exp_bits:
         _check_rows("exp", exp, n, words_for(exp_bits))
     _check_idx(ctx_idx, n, ctx)
-    flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0)
+    flags = (_redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0) |
+             (MX_TWO_LANES if two_lanes else 0))
     _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,
                               window, _ptr(out), n, flags, _stream_ptr(stream)))
     return out
@@ -314,7 +318,7 @@ def modexp_ws_bytes(ctx, n, window=0, block=False):
 
 
 def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, plain=False, stream=None,
-              block=False, n=None, one_lane=False, cios=False):
+              block=False, n=None, one_lane=False, cios=False, two_lanes=False):
     """modexp with a caller-owned workspace tensor (uint8/any dtype, device); n rows of base/exp used."""
     n = base.shape[0] if n is None else n
     if out is None:
@@ -333,10 +337,32 @@ def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, pl
         raise ValueError("n exceeds the context count (pass ctx_idx)")
     if not ws.is_cuda or not ws.is_contiguous():
         raise ValueError("ws: expected a contiguous device tensor")
-    flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0)
+    flags = (_redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0) |
+             (MX_TWO_LANES if two_lanes else 0))
     _check(lib().modexp_batch_ws(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None,
                                  exp_bits, window, _ptr(out), n, flags, _ptr(ws), ws.numel() * ws.element_size(),
                                  _stream_ptr(stream)))
+    return out
+
+
+def rsa_crt(ctx_p, ctx_q, c, dp, dq, qinv, window=0, out=None, key_idx=None, plain=False, cios=False, stream=None):
+    """RSA private-key operation by the CRT (rsa_crt_batch): c^d mod p q per instance.
+
+    ctx_p, ctx_q: Contexts of the primes (same class, 1024 or 2048 bits); c, out: int64 [n, 2 W];
+    dp, dq, qinv: int64 [n, W] with W = bits / 64; key_idx: int32 device tensor or None."""
+    n = c.shape[0]
+    W = ctx_p.words
+    if out is None:
+        import torch
+        out = torch.empty_like(c)
+    for nm, t, w in (("c", c, 2 * W), ("out", out, 2 * W), ("dp", dp, W), ("dq", dq, W), ("qinv", qinv, W)):
+        _check_rows(nm, t, n, w)
+    if key_idx is not None:
+        _check_idx(key_idx, n, ctx_p)
+    elif n > min(ctx_p.count, ctx_q.count):
+        raise ValueError("n exceeds the key count (pass key_idx)")
+    _check(lib().rsa_crt_batch(ctx_p.handle, ctx_q.handle, _ptr(key_idx), _ptr(c), _ptr(dp), _ptr(dq), _ptr(qinv),
+                               window, _ptr(out), n, _redc_flags(plain, cios), _stream_ptr(stream)))
     return out
 
 

@@ -209,10 +209,12 @@ class GpuExecutor:
     queue.
     """
 
-    def __init__(self, trace, max_batch, mem_budget, windows=None, max_slots=4, device="cuda", one_lane_from=16384):
+    def __init__(self, trace, max_batch, mem_budget, windows=None, max_slots=4, device="cuda", one_lane_from=16384,
+                 two_lanes_from=4096):
         import torch
         self.torch = torch
         self.one_lane_from = one_lane_from
+        self.two_lanes_from = two_lanes_from
         self.classes = trace.classes
         self.ctx = {c: mx.Context(trace.mods[c], c) for c in self.classes}
         self.windows = windows or {c: 0 for c in self.classes}
@@ -244,11 +246,13 @@ class GpuExecutor:
     def launch(self, slot, c, lo, hi):
         torch = self.torch
         st = slot["stream"]
-        # a large batch means a loaded device: the block kernels then keep one lane per
-        # instance (throughput); small batches run two lanes per instance (latency)
+        # the batch size tells the load: the block kernels keep one lane per instance for
+        # large batches (throughput), at most two for middle-sized ones, and run four lanes per
+        # instance for small ones (latency of a lightly loaded device)
+        n = hi - lo
         mx.modexp_ws(self.ctx[c], self.base[c][lo:hi], self.exp[c][lo:hi], c, slot["ws"], window=self.windows[c],
                      out=self.out[c][lo:hi], ctx_idx=self.cidx[c][lo:hi], stream=st,
-                     one_lane=hi - lo >= self.one_lane_from)
+                     one_lane=n >= self.one_lane_from, two_lanes=self.two_lanes_from <= n < self.one_lane_from)
         ev = torch.cuda.Event()
         ev.record(st)
         slot["event"] = ev

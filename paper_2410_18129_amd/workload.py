@@ -7,11 +7,15 @@ exponentiation arithmetic.  The paper measures on random operands only
   * modulus: ``bits`` uniform bits, then the top bit and bit 0 set;
   * base: uniform in [0, N) by rejection on ``bits``-bit draws;
   * exponent: ``ebits`` uniform bits;
-  * lazy Montgomery operands: uniform in [0, 2N).
+  * lazy Montgomery operands: uniform in [0, 2N);
+  * RSA keys (CRT form) from pairs of seeded primes, e = 65537, messages uniform
+    below p q (key preparation is input generation, not the method).
 
 Streams: ``numpy.random.Generator(PCG64(SeedSequence(SEED_BASE + k)))`` for
 workload k, with named sub-streams spawned from it.
 """
+import math
+
 import numpy as np
 
 SEED_BASE = 2410181290
@@ -160,3 +164,48 @@ def zipf_ranks(g, count, nitems, s=1.1):
 def poisson_arrivals(g, count, rate):
     """Arrival times (seconds) of a Poisson process with ``rate`` per second."""
     return np.cumsum(g.exponential(1.0 / rate, size=count))
+
+
+def rsa_keys(primes, e=65537):
+    """RSA keys in CRT form from consecutive pairs of distinct primes.
+
+    Each key is a dict with p, q, n = p q, e, d = e^{-1} mod lcm(p-1, q-1),
+    dp = d mod (p-1), dq = d mod (q-1) and qinv = q^{-1} mod p (the private
+    key layout of PKCS #1).  A pair whose lcm(p-1, q-1) shares a factor with
+    e is skipped.
+    """
+    keys = []
+    for i in range(0, len(primes) - 1, 2):
+        p, q = primes[i], primes[i + 1]
+        if p == q:
+            continue
+        lam = (p - 1) * (q - 1) // math.gcd(p - 1, q - 1)
+        if math.gcd(e, lam) != 1:
+            continue
+        d = pow(e, -1, lam)
+        keys.append({"p": p, "q": q, "n": p * q, "e": e, "d": d, "dp": d % (p - 1), "dq": d % (q - 1),
+                     "qinv": pow(q, -1, p)})
+    return keys
+
+
+def rsa_messages(g, keys, key_of):
+    """One message per instance, uniform below the modulus of its key (key_of[i]), by rejection."""
+    out = []
+    for k in key_of:
+        n = keys[int(k)]["n"]
+        nb = n.bit_length()
+        while True:
+            v = int.from_bytes(random_words(g, nb, 1)[0].tobytes(), "little")
+            if v < n:
+                break
+        out.append(v)
+    return out
+
+
+def load_primes(bits):
+    """The committed seeded primes of tests/golden/primes_<bits>.txt (written by make_primes.py there)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
+                        "primes_%d.txt" % bits)
+    with open(path) as f:
+        return [int(l, 16) for l in f if l.strip() and not l.startswith("#")]

@@ -50,6 +50,7 @@ def test_host_side_argument_errors_without_gpu():
     assert L.mont_ctx_init(ctypes.byref(h), odd.ctypes.data_as(ctypes.c_void_p), 64, 0, None) == mx.MX_EINVAL
     assert L.mont_mul_batch(None, None, None, None, None, 1, 0, None) == mx.MX_EINVAL
     assert L.modexp_batch(None, None, None, None, 8, 5, None, 1, 0, None) == mx.MX_EINVAL
+    assert L.rsa_crt_batch(None, None, None, None, None, None, None, 0, None, 1, 0, None) == mx.MX_EINVAL
 
 
 def test_header_constants_match_the_binding():
@@ -58,9 +59,10 @@ def test_header_constants_match_the_binding():
     src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
     vals = dict((k, int(v)) for k, v in re.findall(r"\b(MX_[A-Z_]+)\s*=\s*(\d+)", src))
     for name in ("MX_OK", "MX_EINVAL", "MX_ENOMEM", "MX_EDEVICE", "MX_EUNSUPPORTED", "MX_REDC_TRUNC",
-                 "MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS"):
+                 "MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS", "MX_TWO_LANES"):
         assert vals[name] == getattr(montexp, name), name
-    flags = [vals[k] for k in ("MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS")]
+    flags = [vals[k] for k in ("MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS",
+                               "MX_TWO_LANES")]
     assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)
 
 

@@ -86,6 +86,9 @@ def test_block_kernel_one_two_and_four_lanes_per_instance_agree(mx):
     forced = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
                                 ctx_idx=idx, one_lane=True))  # MX_ONE_LANE: one lane per instance at any size
     assert forced == one[lo:hi]
+    capped = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
+                                ctx_idx=idx, two_lanes=True))  # MX_TWO_LANES: two lanes where four would run
+    assert capped == one[lo:hi]
     M, Bs, Es = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
     for i in (0, 32767, 32768, n - 1):
         assert one[i] == oracle.modexp(Bs[i], Es[i], M[i], bits)

@@ -251,6 +251,9 @@ def test_errors_and_noops(mx):
     with pytest.raises(mx.MontError) as ei:
         mx.modexp(ctx, one, one, 8, plain=True, cios=True)
     assert ei.value.status == mx.MX_EINVAL
+    with pytest.raises(mx.MontError) as ei:  # MX_ONE_LANE and MX_TWO_LANES exclude each other
+        mx.modexp(ctx, one, one, 8, one_lane=True, two_lanes=True)
+    assert ei.value.status == mx.MX_EINVAL
     ctx.close()
     # CIOS exists for the register-resident kernels only: not for the block kernels or above 2048 bits
     for bits, block in ((2048, True), (3072, False)):
