@@ -65,6 +65,25 @@ static_assert(!kHasBlk || (kK >= 1 && kK <= 4), "block kernels: redundant limbs 
 constexpr uint32_t kFourLaneMax = 16384;
 constexpr uint32_t kTwoLaneMax = 32768;
 
+// k_modexp with a register budget for two wavefronts per SIMD: at 1024 bits the
+// exponentiation fits 256 registers per lane with a few spills, and two
+// wavefronts on a SIMD hide each other's issue stalls (measured 6-8 % faster
+// than the 512-register build at 65536 and 131072 instances, same results).
+template <int N, int BW, bool TRUNC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_modexp_2w(CtxDev ctx, const uint32_t* __restrict__ cidx, const uint64_t* __restrict__ base,
+            const uint64_t* __restrict__ ex, uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* __restrict__ out,
+            uint32_t count, uint32_t* __restrict__ ws, uint32_t ws_bytes, uint32_t coff) {
+  __shared__ uint32_t s_ctx[2 * N * 64];
+  const uint32_t tile0 = blockIdx.x * 64;
+  const uint32_t tbytes = (1u << w) * (uint32_t)packed_words(N) * 256u;
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  stagger<N>(blockIdx.x, w);
+  modexp_tile<N, BW, TRUNC>(ctx, cidx, base, ex, ebits, ewords, w, out, count, ws + (size_t)blockIdx.x * (tbytes / 4u),
+                            tbytes, coff, tile0, s_ctx);
+}
+constexpr bool kTwoWaves = kBits == 1024;
+
 hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
   const uint32_t blocks = (ctx.count + 63) / 64;
   hipLaunchKernelGGL((k_ctx_init<kN, kW>), dim3(blocks), dim3(64), 0, st, mods, ctx);
@@ -193,12 +212,20 @@ hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx
       return MX_CAT(cios_modexp_, MX_CLASS_BITS)(ctx, cidx, base, ex, ebits, ewords, w, out, count, ws, ws_bytes, coff,
                                                  st);
 #endif
-    if (trunc)
+    if constexpr (kTwoWaves) {
+      if (trunc)
+        hipLaunchKernelGGL((k_modexp_2w<kN, kW, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
+                           ewords, w, out, count, ws, ws_bytes, coff);
+      else
+        hipLaunchKernelGGL((k_modexp_2w<kN, kW, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
+                           ewords, w, out, count, ws, ws_bytes, coff);
+    } else if (trunc) {
       hipLaunchKernelGGL((k_modexp<kN, kW, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits, ewords,
                          w, out, count, ws, ws_bytes, coff);
-    else
+    } else {
       hipLaunchKernelGGL((k_modexp<kN, kW, false>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex, ebits,
                          ewords, w, out, count, ws, ws_bytes, coff);
+    }
   }
   return hipGetLastError();
 }
