@@ -122,7 +122,9 @@ mx_status mont_sqr_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uin
  * and leading zeros are processed; bits above exp_bits are ignored.
  * exp_bits = 0 gives 1 (also 0^0 = 1).  window in 1..8, 0 = library choice.
  * The library-owned workspace (2^w * r_bits/8 bytes per instance) grows on
- * demand; a growth allocates device memory.  out may alias base. */
+ * demand; a growth allocates device memory.  Calls on one context share that
+ * workspace: the host side is serialised, the device work is not, so issue
+ * them on one stream (or use modexp_batch_ws).  out may alias base. */
 mx_status modexp_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint64_t *base, const uint64_t *exp,
                        uint32_t exp_bits, uint32_t window, uint64_t *out, uint32_t n, uint32_t flags,
                        void *stream);
@@ -157,7 +159,8 @@ mx_status modexp_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t window, uint
  * MX_REDC_CIOS) apply to the two exponentiations.  out may alias c but not
  * dp, dq or qinv.  The two intermediates (n W words each) live in a buffer
  * owned by ctx_p that grows on demand (a growth allocates device memory), next
- * to the exponentiation workspaces of both contexts. */
+ * to the exponentiation workspaces of both contexts; as for modexp_batch,
+ * calls sharing a context must be issued on one stream. */
 mx_status rsa_crt_batch(const mont_ctx *ctx_p, const mont_ctx *ctx_q, const uint32_t *key_idx, const uint64_t *c,
                         const uint64_t *dp, const uint64_t *dq, const uint64_t *qinv, uint32_t window,
                         uint64_t *out, uint32_t n, uint32_t flags, void *stream);
