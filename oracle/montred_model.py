@@ -1,7 +1,9 @@
 """Limb-level model of the truncated Montgomery reduction -- TEST INFRASTRUCTURE.
 
 Written from Section 5 (Algorithm 6, Theorem 1, Theorem 2 and equations
-(1)-(5)); ``redc_cios`` from Section 4 (Algorithm 4).  It is a checker of the *reading* of the paper, not part of the GPU
+(1)-(5)); ``redc_cios`` from Section 4 (Algorithm 4); ``kara_columns`` and
+``redc_truncated_karatsuba`` from Section 3 and the Karatsuba part of
+Section 5.  It is a checker of the *reading* of the paper, not part of the GPU
 library, and shares nothing with it.
 
 Setting: limbs of L bits, R = 2^(L*n), N odd with 4N <= R, T < 4N^2,
@@ -195,6 +197,77 @@ def redc_cios(A, B, N, L, n):
         Y[0] += carry
     peak = max(peak, max(Y))
     return sum(y << (L * j) for j, y in enumerate(Y)), peak
+
+
+def kara_columns(a, b, levels, xmin=0):
+    """Column sums of the product of two limb vectors (lists of equal length k), by Karatsuba.
+
+    Returns (cols, products): cols[x] = sum_{i+j=x} a_i b_j for x >= xmin
+    (None below), products = the multiplications used.  Section 3: the
+    operands split at m = ceil(k/2) limbs, a = a0 + B a1, b = b0 + B b1, and
+    D0 = a0 b0, D1 = (a0 + a1)(b0 + b1), D2 = a1 b1.  The half sums are taken
+    limb by limb, without carries, so the recombination D1 - D0 - D2 =
+    a0 b1 + a1 b0 holds for every column on its own, not only for the whole
+    number.  Column x of the product is then D0[x] + (D1 - D0 - D2)[x - m]
+    + D2[x - 2m], and only the sub-columns that reach columns >= xmin are
+    formed (the truncation of Section 5 applied to the sub-products).
+    levels = 0 is the schoolbook product restricted to those columns.
+    """
+    k = len(a)
+    ncol = 2 * k - 1
+    if levels == 0 or k < 2:
+        cols = [None] * ncol
+        cnt = 0
+        for x in range(max(xmin, 0), ncol):
+            v = 0
+            for i in range(max(0, x - k + 1), min(x, k - 1) + 1):
+                v += a[i] * b[x - i]
+                cnt += 1
+            cols[x] = v
+        return cols, cnt
+    m = (k + 1) // 2
+    a0, a1 = a[:m], a[m:] + [0] * (2 * m - k)
+    b0, b1 = b[:m], b[m:] + [0] * (2 * m - k)
+    sa = [x + y for x, y in zip(a0, a1)]
+    sb = [x + y for x, y in zip(b0, b1)]
+    d0, c0 = kara_columns(a0, b0, levels - 1, min(xmin, xmin - m))
+    d1, c1 = kara_columns(sa, sb, levels - 1, xmin - m)
+    d2, c2 = kara_columns(a1, b1, levels - 1, xmin - 2 * m)
+    cols = [None] * ncol
+    for x in range(max(xmin, 0), ncol):
+        v = 0
+        if x <= 2 * m - 2:
+            v += d0[x]
+        y = x - m
+        if 0 <= y <= 2 * m - 2:
+            v += d1[y] - d0[y] - d2[y]
+        z = x - 2 * m
+        if 0 <= z <= 2 * m - 2:
+            v += d2[z]
+        cols[x] = v
+    return cols, c0 + c1 + c2
+
+
+def redc_truncated_karatsuba(T, N, L, n, levels=1):
+    """Algorithm 6 with the truncated high half of q*N formed by Karatsuba (Section 5, Karatsuba).
+
+    Only the columns n-2 .. 2n-2 of q*N are formed, through kara_columns;
+    they equal the schoolbook columns, so the exact two-column carry reading
+    of redc_truncated_fullcol applies unchanged.  Returns (C, products of the
+    q*N part).
+    """
+    R = 1 << (L * n)
+    M = (1 << L) - 1
+    Np = (-pow(N, -1, R)) % R
+    q = (T * Np) % R
+    cols, cnt = kara_columns(limbs(q, L, n), limbs(N, L, n), levels, n - 2)
+    P = cols + [0]
+    Tl = limbs(T, L, 2 * n)
+    a2 = Tl[n - 2] + P[n - 2]
+    a1 = Tl[n - 1] + P[n - 1] + (a2 >> L)
+    k = (a1 >> L) + (1 if ((a1 & M) | (a2 & M)) else 0)
+    H = sum(P[w] << (L * (w - n)) for w in range(n, 2 * n - 1))
+    return (T >> (L * n)) + H + k, cnt
 
 
 def fullcol_condition(L, n):

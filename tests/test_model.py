@@ -153,3 +153,59 @@ def test_cios_and_truncated_counts():
         assert c["sqr_trunc"] < c["sqr_cios"]
         # the multiplication counts differ by n - 1: 2n^2 + 2n - 1 against 2n^2 + n
         assert c["mul_trunc"] - c["mul_cios"] == n - 1
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_karatsuba_columns_equal_schoolbook_columns(levels):
+    """Limb-wise half sums make D1 - D0 - D2 exact column by column, so every column matches the schoolbook's."""
+    rng = random.Random(400 + levels)
+    for k in (1, 2, 3, 4, 5, 7, 8, 19, 37, 74):
+        a = [rng.getrandbits(28) for _ in range(k)]
+        b = [rng.getrandbits(28) for _ in range(k)]
+        sb, cnt_sb = m.kara_columns(a, b, 0)
+        assert cnt_sb == k * k
+        for xmin in sorted({0, k - 2, k - 1, k, 2 * k - 2}):
+            got, _ = m.kara_columns(a, b, levels, xmin)
+            for x in range(max(xmin, 0), 2 * k - 1):
+                assert got[x] == sb[x], (k, levels, xmin, x)
+
+
+@pytest.mark.parametrize("L,n", [(2, 2), (3, 2), (4, 2), (3, 3), (2, 4), (3, 4)])
+def test_truncated_karatsuba_reduction_exhaustive(L, n):
+    for N, T in _cases(L, n, 200):
+        if not m.fullcol_condition(L, n):
+            continue
+        e = m.redc_exact(T, N, L, n)
+        for levels in (1, 2):
+            got, _ = m.redc_truncated_karatsuba(T, N, L, n, levels)
+            assert got == e, (L, n, N, T, levels)
+
+
+@pytest.mark.parametrize("n", [4, 37, 74, 111, 148])
+def test_truncated_karatsuba_reduction_random_at_28bit_limbs(n):
+    rng = random.Random(500 + n)
+    L = 28
+    t = L * n - 2
+    for trial in range(6):
+        N = rng.getrandbits(t) | 1 | (1 << (t - 1))
+        T = [0, (2 * N - 1) ** 2][trial] if trial < 2 else rng.randrange(4 * N * N)
+        e = m.redc_exact(T, N, L, n)
+        for levels in (1, 2):
+            got, _ = m.redc_truncated_karatsuba(T, N, L, n, levels)
+            assert got == e, (n, trial, levels)
+
+
+def test_truncated_karatsuba_counts():
+    """One level: the truncated high half of q*N costs about two thirds of a whole one-level Karatsuba product
+    (D2 whole, the upper halves of D1 and D0), i.e. about n^2 / 2, the truncated schoolbook's leading term."""
+    for n in (74, 148):
+        mm = (n + 1) // 2
+        rng = random.Random(n)
+        q = [rng.getrandbits(28) for _ in range(n)]
+        N = [rng.getrandbits(28) for _ in range(n)]
+        _, full = m.kara_columns(q, N, 1, 0)
+        _, trunc = m.kara_columns(q, N, 1, n - 2)
+        assert full == 3 * mm * mm
+        assert 0.6 < trunc / full < 0.72, trunc / full
+        sb_trunc = n * (n + 1) // 2 + n - 1
+        assert abs(trunc - sb_trunc) < 3 * n, (trunc, sb_trunc)
