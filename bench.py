@@ -223,7 +223,8 @@ def main():
     for op, fn in (("mul", lambda kw: mx.mont_mul(b2.ctx, A, B, out=O, stream=stream, **kw)),
                    ("sqr", lambda kw: mx.mont_sqr(b2.ctx, A, out=O, stream=stream, **kw))):
         rates = {}
-        for r, kw in (("trunc", {}), ("plain", {"plain": True}), ("cios", {"cios": True})):
+        for r, kw in (("trunc", {}), ("plain", {"plain": True}), ("cios", {"cios": True}),
+                      ("kara", {"kara_redc": True})):
             wl_, kk = time_launches(lambda: fn(kw), 20, 3, stream)
             rates[r] = n * 20 / wl_
             if r == "trunc":
@@ -233,6 +234,9 @@ def main():
         res["mod%s_trunc_speedup" % op] = rates["trunc"] / rates["plain"]
         res["mod%s_cios_per_s" % op] = rates["cios"]
         res["mod%s_trunc_vs_cios" % op] = rates["trunc"] / rates["cios"]
+        # the truncated high half of q*N by one-level Karatsuba (the same products, more additions)
+        res["mod%s_kara_redc_per_s" % op] = rates["kara"]
+        res["mod%s_trunc_vs_kara_redc" % op] = rates["trunc"] / rates["kara"]
     b2.ctx.close()
     progress("modmul / modsqr done")
     del b2

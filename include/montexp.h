@@ -72,11 +72,18 @@ enum {
                           same results.  Register-resident classes (<= 2048
                           bits) only, else MX_EUNSUPPORTED; with MX_REDC_PLAIN,
                           MX_EINVAL; not in the mixed launch                 */
-  MX_TWO_LANES = 32    /* exponentiation with the block kernels: at most two
+  MX_TWO_LANES = 32,   /* exponentiation with the block kernels: at most two
                           lanes per instance (batches of at most 16384 would
                           otherwise run four); a middle ground between latency
                           and throughput for a moderately loaded device; with
                           MX_ONE_LANE, MX_EINVAL; same results               */
+  MX_REDC_KARATSUBA = 64 /* mont_mul_batch / mont_sqr_batch only: the truncated
+                          high half of q N formed by one-level Karatsuba
+                          (Section 5, Karatsuba paragraph) from limb-wise half
+                          sums, so that every column is the schoolbook's;
+                          same results.  Register-resident classes (<= 2048
+                          bits), else MX_EUNSUPPORTED; with another MX_REDC_
+                          flag, MX_EINVAL; exponentiation: MX_EUNSUPPORTED   */
 };
 
 /* Montgomery contexts for `count` moduli of size class `bits` (Section 4:

@@ -106,18 +106,22 @@ static int impl_of(const mont_ctx* ctx, uint32_t flags) {
   return ctx->bits > 2048 && blk != 1 ? blk : 0;
 }
 
-// Reduction of the flags (mx::Redc); -1 if MX_REDC_PLAIN and MX_REDC_CIOS are both set.
+// Reduction of the flags (mx::Redc); -1 if more than one of MX_REDC_PLAIN, MX_REDC_CIOS and
+// MX_REDC_KARATSUBA is set.
 static int redc_of(uint32_t flags) {
-  if ((flags & MX_REDC_PLAIN) && (flags & MX_REDC_CIOS)) return -1;
-  return (flags & MX_REDC_CIOS) ? mx::kRedcCios : (flags & MX_REDC_PLAIN) ? mx::kRedcPlain : mx::kRedcTrunc;
+  const uint32_t r = flags & (uint32_t)(MX_REDC_PLAIN | MX_REDC_CIOS | MX_REDC_KARATSUBA);
+  if (r & (r - 1)) return -1;
+  return (flags & MX_REDC_CIOS) ? mx::kRedcCios : (flags & MX_REDC_KARATSUBA) ? mx::kRedcKara
+       : (flags & MX_REDC_PLAIN) ? mx::kRedcPlain : mx::kRedcTrunc;
 }
 
 // Checks the reduction flags against the kernel family; MX_OK or the failure status.
 static mx_status check_redc(const char* name, const mont_ctx* ctx, int impl, int redc) {
-  if (redc < 0) return fail(MX_EINVAL, "%s: MX_REDC_PLAIN and MX_REDC_CIOS exclude each other", name);
-  if (redc == mx::kRedcCios && (impl != 0 || !ctx->ops->has_cios))
-    return fail(MX_EUNSUPPORTED, "%s: MX_REDC_CIOS is built for the register-resident classes (<= 2048 bits) only",
-                name);
+  if (redc < 0)
+    return fail(MX_EINVAL, "%s: MX_REDC_PLAIN, MX_REDC_CIOS and MX_REDC_KARATSUBA exclude each other", name);
+  if ((redc == mx::kRedcCios || redc == mx::kRedcKara) && (impl != 0 || !ctx->ops->has_cios))
+    return fail(MX_EUNSUPPORTED, "%s: MX_REDC_CIOS and MX_REDC_KARATSUBA are built for the register-resident "
+                "classes (<= 2048 bits) only", name);
   return MX_OK;
 }
 
@@ -246,7 +250,7 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!a || !out || (!sqr && !b)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_REDC_CIOS))
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_REDC_CIOS | MX_REDC_KARATSUBA))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
   const int impl = impl_of(ctx, flags);
   if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
@@ -293,7 +297,7 @@ static mx_status modexp_common(const char* name, mont_ctx* ctx, const uint32_t* 
   if (n == 0) return MX_OK;
   if (!base || !out || (exp_bits && !exp)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
   if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_REDC_CIOS |
-                          MX_TWO_LANES))
+                          MX_TWO_LANES | MX_REDC_KARATSUBA))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
   if ((flags & MX_ONE_LANE) && (flags & MX_TWO_LANES))
     return fail(MX_EINVAL, "%s: MX_ONE_LANE and MX_TWO_LANES exclude each other", name);
@@ -301,6 +305,8 @@ static mx_status modexp_common(const char* name, mont_ctx* ctx, const uint32_t* 
   if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
   const int redc = redc_of(flags);
   if (mx_status rs = check_redc(name, ctx, impl, redc); rs != MX_OK) return rs;
+  if (redc == mx::kRedcKara)
+    return fail(MX_EUNSUPPORTED, "%s: MX_REDC_KARATSUBA is built for mont_mul_batch / mont_sqr_batch only", name);
   if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   const uint32_t w = window ? window : default_window(ctx->bits);
@@ -369,6 +375,7 @@ mx_status rsa_crt_batch(const mont_ctx* ctx_p, const mont_ctx* ctx_q, const uint
   if (n == 0) return MX_OK;
   if (!c || !dp || !dq || !qinv || !out) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
   if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_REDC_CIOS)) return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
+  // (MX_REDC_KARATSUBA is rejected here as an unknown flag: it has no exponentiation kernel)
   if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
   const uint32_t cnt_min = ctx_p->count < ctx_q->count ? ctx_p->count : ctx_q->count;
   if (!key_idx && n > cnt_min) return fail(MX_EINVAL, "%s: n=%u exceeds the key count %u", name, n, cnt_min);

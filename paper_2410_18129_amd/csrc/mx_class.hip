@@ -2,11 +2,15 @@
 // -DMX_CLASS_BITS=<bits>; each object exports mx::class_ops_<bits>().
 // Classes up to 2048 bits use the register-resident kernels (mx_kernels.hpp);
 // larger classes use the block-level schoolbook (mx_block.hpp).  The
-// word-interleaved kernels (Algorithm 4) of a register-resident class are
-// built separately, with -DMX_CIOS_UNIT as well, so that they compile in
-// parallel with the rest of the class; that object exports the launchers
-// cios_mont_<bits> and cios_modexp_<bits>.
+// alternative-reduction kernels of a register-resident class (the
+// word-interleaved multiplication of Algorithm 4, and the Karatsuba-truncated
+// reduction) are built separately, with -DMX_CIOS_UNIT as well, so that they
+// compile in parallel with the rest of the class; that object exports the
+// launchers cios_mont_<bits>, cios_modexp_<bits> and kredc_mont_<bits>.
 #include "mx_block.hpp"
+#ifdef MX_CIOS_UNIT
+#include "mx_kredc.hpp"
+#endif
 
 #ifndef MX_CLASS_BITS
 #error "MX_CLASS_BITS must be defined"
@@ -25,11 +29,26 @@ hipError_t MX_CAT(cios_modexp_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t
                                                const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w,
                                                uint64_t* out, uint32_t count, uint32_t* ws, uint32_t ws_bytes,
                                                uint32_t coff, hipStream_t st);
+hipError_t MX_CAT(kredc_mont_, MX_CLASS_BITS)(bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
+                                              const uint64_t* b, uint64_t* out, uint32_t count, uint32_t coff,
+                                              hipStream_t st);
 #endif
 
 #ifdef MX_CIOS_UNIT
 static_assert(MX_CLASS_BITS <= 2048, "the word-interleaved kernels exist for the register-resident classes");
 constexpr int kCiosN = limbs_for(MX_CLASS_BITS);
+hipError_t MX_CAT(kredc_mont_, MX_CLASS_BITS)(bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
+                                              const uint64_t* b, uint64_t* out, uint32_t count, uint32_t coff,
+                                              hipStream_t st) {
+  constexpr int RW = words_for(28 * kCiosN);
+  if (sqr)
+    hipLaunchKernelGGL((k_mont_kredc<kCiosN, RW, true>), dim3((count + 63) / 64), dim3(64), 0, st, ctx, cidx, a, b,
+                       out, count, coff);
+  else
+    hipLaunchKernelGGL((k_mont_kredc<kCiosN, RW, false>), dim3((count + 63) / 64), dim3(64), 0, st, ctx, cidx, a, b,
+                       out, count, coff);
+  return hipGetLastError();
+}
 hipError_t MX_CAT(cios_mont_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
                                              const uint64_t* b, uint64_t* out, uint32_t count, uint32_t coff,
                                              hipStream_t st) {
@@ -140,6 +159,7 @@ hipError_t mont_fn(int impl, int redc, bool sqr, const CtxDev& ctx, const uint32
 #if MX_CLASS_BITS <= 2048
     // a square is the product with b = a (the caller passes a twice)
     if (redc == kRedcCios) return MX_CAT(cios_mont_, MX_CLASS_BITS)(ctx, cidx, a, b, out, count, coff, st);
+    if (redc == kRedcKara) return MX_CAT(kredc_mont_, MX_CLASS_BITS)(sqr, ctx, cidx, a, b, out, count, coff, st);
 #endif
 #define MX_L(T, S) \
   hipLaunchKernelGGL((k_mont<kN, kRW, T, S>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count, coff)

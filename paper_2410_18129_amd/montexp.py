@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmontexp.so")
 MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EUNSUPPORTED = 0, 1, 2, 3, 4
 MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA, MX_ONE_LANE, MX_REDC_CIOS, MX_TWO_LANES = \
     0, 1, 2, 4, 8, 16, 32
+MX_REDC_KARATSUBA = 64
 SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
@@ -201,7 +202,8 @@ def _check_idx(ctx_idx, n, ctx):
         raise ValueError("ctx_idx: expected int32 device tensor [%d]" % n)
 
 
-def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=False, cios=False):
+def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=False, cios=False,
+             kara_redc=False):
     """REDC(a*b) per instance; a, b: int64 device tensors [n, mont_words]."""
     n = a.shape[0]
     if out is None:
@@ -210,13 +212,14 @@ def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=
     for nm, t in (("a", a), ("b", b), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    flags = _redc_flags(plain, cios) | _impl_flags(block)
+    flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_REDC_KARATSUBA if kara_redc else 0)
     _check(lib().mont_mul_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(b), _ptr(out), n, flags,
                                 _stream_ptr(stream)))
     return out
 
 
-def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=False, cios=False):
+def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=False, cios=False,
+             kara_redc=False):
     """REDC(a^2) per instance; a: int64 device tensor [n, mont_words]."""
     n = a.shape[0]
     if out is None:
@@ -225,7 +228,7 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=Fal
     for nm, t in (("a", a), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    flags = _redc_flags(plain, cios) | _impl_flags(block)
+    flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_REDC_KARATSUBA if kara_redc else 0)
     _check(lib().mont_sqr_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(out), n, flags, _stream_ptr(stream)))
     return out
 

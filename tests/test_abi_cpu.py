@@ -59,10 +59,11 @@ def test_header_constants_match_the_binding():
     src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
     vals = dict((k, int(v)) for k, v in re.findall(r"\b(MX_[A-Z_]+)\s*=\s*(\d+)", src))
     for name in ("MX_OK", "MX_EINVAL", "MX_ENOMEM", "MX_EDEVICE", "MX_EUNSUPPORTED", "MX_REDC_TRUNC",
-                 "MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS", "MX_TWO_LANES"):
+                 "MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS", "MX_TWO_LANES",
+                 "MX_REDC_KARATSUBA"):
         assert vals[name] == getattr(montexp, name), name
     flags = [vals[k] for k in ("MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS",
-                               "MX_TWO_LANES")]
+                               "MX_TWO_LANES", "MX_REDC_KARATSUBA")]
     assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)
 
 

@@ -40,6 +40,15 @@ def _redcs(bits):
     return r
 
 
+def _mont_redcs(bits):
+    """As _redcs, plus (single operations only, up to 2048 bits) the truncated high half of q*N formed by
+    one-level Karatsuba (Section 5)."""
+    r = _redcs(bits)
+    if bits <= 2048:
+        r["kara"] = {"kara_redc": True}
+    return r
+
+
 @pytest.mark.parametrize("bits", CLASSES)
 def test_context_constants(mx, bits):
     mods = _moduli(bits, 70)  # 70: one full wavefront and a ragged tail
@@ -68,7 +77,7 @@ def test_mont_mul_sqr_random(mx, bits, count):
     B = wl.random_below(g, mods, bits, scale=2)
     a, b = ints_dev(A, ctx.mont_words), ints_dev(B, ctx.mont_words)
     outs = {}
-    redcs = _redcs(bits)
+    redcs = _mont_redcs(bits)
     for r, kw in redcs.items():
         outs[("mul", r)] = dev_ints(mx.mont_mul(ctx, a, b, **kw))
         outs[("sqr", r)] = dev_ints(mx.mont_sqr(ctx, a, **kw))
@@ -101,7 +110,7 @@ def test_mont_mul_adversarial(mx, bits):
     rb = ctx.r_bits
     a = ints_dev([p[1] for p in pairs], ctx.mont_words)
     b = ints_dev([p[2] for p in pairs], ctx.mont_words)
-    for r, kw in _redcs(bits).items():
+    for r, kw in _mont_redcs(bits).items():
         got = dev_ints(mx.mont_mul(ctx, a, b, **kw))
         gsq = dev_ints(mx.mont_sqr(ctx, a, **kw))
         for i, (N, x, y) in enumerate(pairs):
@@ -254,6 +263,15 @@ def test_errors_and_noops(mx):
     with pytest.raises(mx.MontError) as ei:  # MX_ONE_LANE and MX_TWO_LANES exclude each other
         mx.modexp(ctx, one, one, 8, one_lane=True, two_lanes=True)
     assert ei.value.status == mx.MX_EINVAL
+    with pytest.raises(mx.MontError) as ei:  # one reduction at a time
+        mx.mont_sqr(ctx, a[:1], cios=True, kara_redc=True)
+    assert ei.value.status == mx.MX_EINVAL
+    # the Karatsuba-truncated reduction has no exponentiation kernel
+    import ctypes
+    ob = torch.zeros((1, 1), dtype=torch.int64, device="cuda")
+    assert mx.lib().modexp_batch(ctx.handle, None, ctypes.c_void_p(one.data_ptr()), ctypes.c_void_p(one.data_ptr()),
+                                 8, 0, ctypes.c_void_p(ob.data_ptr()), 1, mx.MX_REDC_KARATSUBA,
+                                 None) == mx.MX_EUNSUPPORTED
     ctx.close()
     # CIOS exists for the register-resident kernels only: not for the block kernels or above 2048 bits
     for bits, block in ((2048, True), (3072, False)):
@@ -262,6 +280,9 @@ def test_errors_and_noops(mx):
         x = torch.zeros((1, c.mont_words), dtype=torch.int64, device="cuda")
         with pytest.raises(mx.MontError) as ei:
             mx.mont_sqr(c, x, cios=True, block=block)
+        assert ei.value.status == mx.MX_EUNSUPPORTED
+        with pytest.raises(mx.MontError) as ei:
+            mx.mont_mul(c, x, x, kara_redc=True, block=block)
         assert ei.value.status == mx.MX_EUNSUPPORTED
         xb = torch.zeros((1, c.words), dtype=torch.int64, device="cuda")
         e1 = torch.zeros((1, 1), dtype=torch.int64, device="cuda")
