@@ -318,6 +318,11 @@ def other_workloads(a, mx, counts, dev, stream):
         O = torch.empty_like(A)
         wl_, _ = time_launches(lambda: mx.mont_mul(b3.ctx, A, A, out=O, block=impl, stream=stream), 5, 1, stream)
         c3["modmul_per_s_" + tag] = b3.n * 5 / wl_
+    # the Karatsuba kernel runs one lane per instance; the schoolbook at one lane too, for a like-for-like ratio
+    wl_, k = time_launches(lambda: mx.modexp(b3.ctx, b3.base, b3.exp, 4096, window=6, out=b3.out, block=True,
+                                             one_lane=True, stream=stream), 2, 1, stream)
+    c3["modexp_per_s_schoolbook_one_lane"] = b3.n * 2 / wl_
+    c3["schoolbook_vs_karatsuba_one_lane"] = c3["modexp_per_s_schoolbook_one_lane"] / c3["modexp_per_s_karatsuba"]
     out["c3_4096x16384"] = c3
     progress("16384 x 4096-bit done")
     out["rsa2048_crt"] = rsa_crt_workload(mx, counts, dev, stream)
