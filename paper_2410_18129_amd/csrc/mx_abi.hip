@@ -404,11 +404,24 @@ mx_status rsa_crt_batch(const mont_ctx* ctx_p, const mont_ctx* ctx_q, const uint
   hipError_t e = bits == 1024 ? mx::crt_reduce_1024(cp->dev, cq->dev, key_idx, c, xp, xq, n, 0, st)
                               : mx::crt_reduce_2048(cp->dev, cq->dev, key_idx, c, xp, xq, n, 0, st);
   if (e != hipSuccess) return dev_fail(e, name);
-  // the two half-size exponentiations, in place (modexp_batch's output may alias its base)
-  mx_status ms = modexp_common(name, cp, key_idx, xp, dp, bits, window, xp, n, flags, nullptr, 0, stream);
-  if (ms != MX_OK) return ms;
-  ms = modexp_common(name, cq, key_idx, xq, dq, bits, window, xq, n, flags, nullptr, 0, stream);
-  if (ms != MX_OK) return ms;
+  // the two half-size exponentiations, in place (the outputs may alias the bases): one
+  // launch over both halves where the class has it and its workspace fits one launch
+  const int redc = redc_of(flags);
+  const uint32_t w = window ? window : default_window(bits);
+  const size_t pair_ws = (size_t)cp->ops->ws_rows(0, true, w) * 64u * sizeof(uint32_t) * 2u * ((n + 63) / 64);
+  if (cp->ops->modexp_pair && redc != mx::kRedcCios && pair_ws <= mx::kMaxWsBytes) {
+    std::lock_guard<std::mutex> wl(cp->ws_mu);
+    mx_status ms = ensure_ws(cp, pair_ws, name);
+    if (ms != MX_OK) return ms;
+    e = cp->ops->modexp_pair(redc == mx::kRedcTrunc, cp->dev, cq->dev, key_idx, xp, dp, dq, bits, W, w, xp, n,
+                             (uint32_t*)cp->ws, (uint32_t)pair_ws, st);
+    if (e != hipSuccess) return dev_fail(e, name);
+  } else {
+    mx_status ms = modexp_common(name, cp, key_idx, xp, dp, bits, window, xp, n, flags, nullptr, 0, stream);
+    if (ms != MX_OK) return ms;
+    ms = modexp_common(name, cq, key_idx, xq, dq, bits, window, xq, n, flags, nullptr, 0, stream);
+    if (ms != MX_OK) return ms;
+  }
   e = bits == 1024 ? mx::crt_garner_1024(cp->dev, cq->dev, key_idx, xp, xq, qinv, out, n, 0, st)
                    : mx::crt_garner_2048(cp->dev, cq->dev, key_idx, xp, xq, qinv, out, n, 0, st);
   if (e != hipSuccess) return dev_fail(e, name);

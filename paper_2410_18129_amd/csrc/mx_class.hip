@@ -103,6 +103,29 @@ k_modexp_2w(CtxDev ctx, const uint32_t* __restrict__ cidx, const uint64_t* __res
 }
 constexpr bool kTwoWaves = kBits == 1024;
 
+// Two batches of `count` instances in one launch of k_modexp_2w's code (the two
+// half-size exponentiations of a CRT-RSA operation): blocks below ceil(count/64)
+// take batch 0 (context c0, exponents e0), the others batch 1 (c1, e1); bases
+// and outputs are one array with batch 1 from instance `count` on.  With two
+// wavefronts per SIMD, one launch over both halves fills both wavefront slots.
+template <int N, int BW, bool TRUNC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_modexp_2w_pair(CtxDev c0, CtxDev c1, const uint32_t* __restrict__ cidx, const uint64_t* __restrict__ base,
+                 const uint64_t* __restrict__ e0, const uint64_t* __restrict__ e1, uint32_t ebits, uint32_t ewords,
+                 uint32_t w, uint64_t* __restrict__ out, uint32_t count, uint32_t* __restrict__ ws,
+                 uint32_t ws_bytes) {
+  __shared__ uint32_t s_ctx[2 * N * 64];
+  const uint32_t nb = (count + 63) / 64;
+  const bool second = blockIdx.x >= nb;
+  const uint32_t tile0 = (blockIdx.x - (second ? nb : 0u)) * 64;
+  const uint32_t tbytes = (1u << w) * (uint32_t)packed_words(N) * 256u;
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  const size_t off = second ? (size_t)count * BW : 0;
+  stagger<N>(blockIdx.x, w);
+  modexp_tile<N, BW, TRUNC>(second ? c1 : c0, cidx, base + off, second ? e1 : e0, ebits, ewords, w, out + off,
+                            count, ws + (size_t)blockIdx.x * (tbytes / 4u), tbytes, 0u, tile0, s_ctx);
+}
+
 hipError_t ctx_fn(const uint64_t* mods, const CtxDev& ctx, hipStream_t st) {
   const uint32_t blocks = (ctx.count + 63) / 64;
   hipLaunchKernelGGL((k_ctx_init<kN, kW>), dim3(blocks), dim3(64), 0, st, mods, ctx);
@@ -251,7 +274,25 @@ hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx
 }
 
 // the word-interleaved kernels (Algorithm 4) exist for the register-resident classes
-const ClassOps kOps = {kBits, kN, kHasBlk || kBlock, kHasKara, !kBlock, ctx_fn, ws_rows_fn, mont_fn, modexp_fn};
+hipError_t modexp_pair_fn(bool trunc, const CtxDev& c0, const CtxDev& c1, const uint32_t* cidx,
+                          const uint64_t* base, const uint64_t* e0, const uint64_t* e1, uint32_t ebits,
+                          uint32_t ewords, uint32_t w, uint64_t* out, uint32_t count, uint32_t* ws, uint32_t ws_bytes,
+                          hipStream_t st) {
+  if constexpr (kTwoWaves) {
+    const uint32_t blocks = 2 * ((count + 63) / 64);
+    if (trunc)
+      hipLaunchKernelGGL((k_modexp_2w_pair<kN, kW, true>), dim3(blocks), dim3(64), 0, st, c0, c1, cidx, base, e0,
+                         e1, ebits, ewords, w, out, count, ws, ws_bytes);
+    else
+      hipLaunchKernelGGL((k_modexp_2w_pair<kN, kW, false>), dim3(blocks), dim3(64), 0, st, c0, c1, cidx, base, e0,
+                         e1, ebits, ewords, w, out, count, ws, ws_bytes);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+const ClassOps kOps = {kBits, kN, kHasBlk || kBlock, kHasKara, !kBlock, ctx_fn, ws_rows_fn, mont_fn, modexp_fn,
+                       kTwoWaves ? modexp_pair_fn : nullptr};
 
 }  // namespace
 

@@ -41,6 +41,14 @@ struct ClassOps {
                        const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w, uint64_t* out,
                        uint32_t count, uint32_t* ws, uint32_t tstride, uint32_t ws_bytes, uint32_t coff,
                        hipStream_t st);
+  // Two exponentiation batches of `count` instances each in one launch (nullptr where not
+  // built): batch 0 on ctx0 with exponents ex0, batch 1 on ctx1 with ex1; bases and outputs
+  // are one array of 2 count instances (batch 1 from instance count on), cidx indexes both
+  // contexts; ws holds 2 ceil(count/64) tile regions of ws_rows(0, true, w) 64 words.
+  hipError_t (*modexp_pair)(bool trunc, const CtxDev& ctx0, const CtxDev& ctx1, const uint32_t* cidx,
+                            const uint64_t* base, const uint64_t* ex0, const uint64_t* ex1, uint32_t ebits,
+                            uint32_t ewords, uint32_t w, uint64_t* out, uint32_t count, uint32_t* ws,
+                            uint32_t ws_bytes, hipStream_t st);
 };
 
 // Largest workspace one launch may use: a buffer descriptor spans < 2 GiB.
