@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 from paper_2410_18129_amd import workload as wl
+from tests import oracle_pool
 from tests.gpu_util import dev_ints, ints_dev
 
 pytestmark = pytest.mark.gpu
@@ -104,13 +105,41 @@ def test_block_flag_unsupported_class(mx):
     ctx.close()
 
 
+def _mixed_host(bits, n, k):
+    mods = wl.random_moduli(wl.stream(k, "moduli"), bits, n)
+    base = wl.random_below_fast(wl.stream(k, "bases"), mods, bits)
+    exps = wl.random_exponents(wl.stream(k, "exps"), bits, n)
+    return mods, base, exps
+
+
+PLAN_COUNTS = {1024: 130, 2048: 70, 3072: 65, 4096: 71}
+
+
+def _plan_idx(bits):
+    """Oracle samples of the small mixed plan: every instance up to 2048 bits, 16 spread over the others."""
+    n = PLAN_COUNTS[bits]
+    return list(range(n)) if bits <= 2048 else sorted({(k * n) // 16 for k in range(16)} | {n - 1})
+
+
+def _plan_jobs(bits):
+    mods, base, exps = _mixed_host(bits, PLAN_COUNTS[bits], 13)
+    M, B, E = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
+    return [(B[i], E[i], M[i], bits) for i in _plan_idx(bits)]
+
+
+def _submit_plan():
+    for bits in PLAN_COUNTS:
+        oracle_pool.submit(("plan", bits), _plan_jobs(bits))
+
+
+ORACLE_JOBS = {"test_mixed_plan_matches_single_class_and_oracle": _submit_plan}
+
+
 def _mixed_inputs(mx, counts, k=13):
     import torch
     batches, ref = [], []
     for bits, n in counts.items():
-        mods = wl.random_moduli(wl.stream(k, "moduli"), bits, n)
-        base = wl.random_below_fast(wl.stream(k, "bases"), mods, bits)
-        exps = wl.random_exponents(wl.stream(k, "exps"), bits, n)
+        mods, base, exps = _mixed_host(bits, n, k)
         ctx = mx.Context(mods, bits)
         b = {"ctx": ctx, "base": mx.to_device(base), "exp": mx.to_device(exps), "exp_bits": bits,
              "out": torch.zeros((n, ctx.words), dtype=torch.int64, device="cuda")}
@@ -121,7 +150,7 @@ def _mixed_inputs(mx, counts, k=13):
 
 def test_mixed_plan_matches_single_class_and_oracle(mx):
     import torch
-    counts = {1024: 130, 2048: 70, 3072: 65, 4096: 71}
+    counts = PLAN_COUNTS
     batches, ref = _mixed_inputs(mx, counts)
     batches[1]["block"] = False
     plan = mx.MixedPlan(batches)
@@ -134,9 +163,8 @@ def test_mixed_plan_matches_single_class_and_oracle(mx):
         got = dev_ints(b["out"])
         alone = dev_ints(mx.modexp(b["ctx"], b["base"], b["exp"], bits, window=plan.windows[list(counts).index(bits)]))
         assert got == alone, bits  # the same result alone and in the mix
-        M, B, E = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
-        i = len(M) - 1
-        assert got[i] == oracle.modexp(B[i], E[i], M[i], bits), bits
+        want = oracle_pool.results(("plan", bits), lambda: _plan_jobs(bits))
+        assert [got[i] for i in _plan_idx(bits)] == want, bits
     plan.close()
     for b in batches:
         b["ctx"].close()

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from paper_2410_18129_amd import workload as wl
+from tests import oracle_pool
 from tests.gpu_util import adversarial_pairs, dev_ints, ints_dev, r_bits
 
 pytestmark = pytest.mark.gpu
@@ -81,7 +82,7 @@ def test_mont_mul_sqr_random(mx, bits, count):
     for r, kw in redcs.items():
         outs[("mul", r)] = dev_ints(mx.mont_mul(ctx, a, b, **kw))
         outs[("sqr", r)] = dev_ints(mx.mont_sqr(ctx, a, **kw))
-    idx = range(count) if count <= 8 or bits <= 512 else [0, 1, 31, 63, 64, count - 1]
+    idx = range(count)
     for i in idx:
         exp_mul = oracle.montmul(A[i], B[i], Ns[i], rb)
         exp_sqr = oracle.montmul(A[i], A[i], Ns[i], rb)
@@ -137,15 +138,33 @@ def test_mont_ctx_idx_indirection(mx):
     ctx.close()
 
 
+def _random_inputs(bits):
+    count = 8 if bits >= 1024 else 70
+    mods = _moduli(bits, count, k=6)
+    base = wl.random_below(wl.stream(6, "bases"), mods, bits)
+    exps = wl.words_to_ints(wl.random_exponents(wl.stream(6, "exps"), bits, count))
+    return mods, base, exps
+
+
+def _random_jobs(bits):
+    mods, base, exps = _random_inputs(bits)
+    return [(b, e, N, bits) for b, e, N in zip(base, exps, wl.words_to_ints(mods))]
+
+
+def _submit_random():
+    for bits in (2048, 3072, 4096):  # the slow classes: every instance, by the oracle pool
+        oracle_pool.submit(("random", bits), _random_jobs(bits))
+
+
+ORACLE_JOBS = {"test_modexp_random": _submit_random}
+
+
 @pytest.mark.parametrize("bits,window", [(64, 1), (64, 3), (128, 4), (256, 2), (512, 4), (1024, 5), (2048, 5),
                                          (2048, 3), (3072, 5), (4096, 6)])
 def test_modexp_random(mx, bits, window):
-    count = 8 if bits >= 1024 else 70
-    g = wl.stream(6, "bases")
-    mods = _moduli(bits, count, k=6)
+    mods, base, exps = _random_inputs(bits)
+    count = len(base)
     Ns = wl.words_to_ints(mods)
-    base = wl.random_below(g, mods, bits)
-    exps = wl.words_to_ints(wl.random_exponents(wl.stream(6, "exps"), bits, count))
     ctx = mx.Context(mods, bits)
     bd = ints_dev(base, ctx.words)
     ed = ints_dev(exps, ctx.words)
@@ -154,9 +173,11 @@ def test_modexp_random(mx, bits, window):
         res[r] = dev_ints(mx.modexp(ctx, bd, ed, bits, window=window, **kw))
     for r in res:
         assert res[r] == res["trunc"], r
-    check = range(count) if bits <= 1024 else range(3 if bits <= 2048 else 1)
-    for i in check:
-        assert res["trunc"][i] == oracle.modexp(base[i], exps[i], Ns[i], bits), i
+    if bits <= 1024:
+        want = [oracle.modexp(base[i], exps[i], Ns[i], bits) for i in range(count)]
+    else:
+        want = oracle_pool.results(("random", bits), lambda: _random_jobs(bits))
+    assert res["trunc"] == want
     ctx.close()
 
 

@@ -132,3 +132,34 @@ def test_oracle_rejects_bad_arguments():
         oracle.redc(5, 4, 8)  # even modulus
     with pytest.raises(ValueError):
         oracle.nprime(10, 8)
+
+
+def test_modexp_many_matches_single_calls_and_pow():
+    """The batch helper behind the CPU baseline's timing computes the same values as one call per
+    instance, with base, exponent and modulus strides that differ (na != nm, ebits not a limb multiple)."""
+    import ctypes
+    lib = oracle._load()
+    rng = random.Random(9)
+    count, na, nm, ebits = 5, 3, 4, 70
+    ne = (ebits + 31) // 32
+    mods = [rng.getrandbits(128) | 1 | (1 << 127) for _ in range(count)]
+    bases = [rng.getrandbits(96) for _ in range(count)]
+    exps = [rng.getrandbits(ebits) for _ in range(count)]
+    exps[1] = 0
+    A = (ctypes.c_uint32 * (count * na))()
+    E = (ctypes.c_uint32 * (count * ne))()
+    M = (ctypes.c_uint32 * (count * nm))()
+    O = (ctypes.c_uint32 * (count * nm))()
+    for k in range(count):
+        for i in range(na):
+            A[k * na + i] = (bases[k] >> (32 * i)) & 0xFFFFFFFF
+        for i in range(ne):
+            E[k * ne + i] = (exps[k] >> (32 * i)) & 0xFFFFFFFF
+        for i in range(nm):
+            M[k * nm + i] = (mods[k] >> (32 * i)) & 0xFFFFFFFF
+    assert lib.ora_modexp_many(A, na, E, ebits, M, nm, O, count) == 0
+    for k in range(count):
+        got = oracle.from_limbs(O[k * nm:(k + 1) * nm])
+        assert got == oracle.modexp(bases[k], exps[k], mods[k], ebits) == pow(bases[k], exps[k], mods[k]), k
+    # the Python wrapper the CPU baseline calls (one limb count for bases and moduli)
+    assert oracle.modexp_many(bases, exps, mods, ebits) == [pow(b, e, N) for b, e, N in zip(bases, exps, mods)]
