@@ -22,13 +22,30 @@
  *  - Canonical values (< N) use words = ceil(bits / 64); Montgomery-domain
  *    values (< 2N) use mont_words = ceil(r_bits / 64).
  *  - The caller owns all operand buffers and the stream; the library owns
- *    context memory and its exponentiation workspace.
- *  - Errors: host-checkable arguments give MX_EINVAL synchronously; launch
- *    or device errors give MX_EDEVICE; mont_last_error() returns a
- *    thread-local message for the last non-OK status.  No call aborts.
+ *    context memory and the context's workspace.  Only mont_ctx_init,
+ *    mont_ctx_reserve, the mixed plan's create call and the autotuner
+ *    allocate device memory; the batch calls never allocate and never wait
+ *    for the device.
+ *  - Streams: a context's constants are read-only once initialised.  Calls
+ *    that use its library workspace (block-kernel single operations,
+ *    modexp_batch, rsa_crt_batch on ctx_p) may come from several host
+ *    threads and streams:
+ *    each makes its stream wait for the workspace's previous user (an event),
+ *    so they take turns on the device.  Calls with a caller workspace
+ *    (modexp_batch_ws, rsa_crt_batch_ws) are independent of each other.
+ *  - Errors: host-checkable arguments give MX_EINVAL synchronously (also a
+ *    launch refused before it is enqueued because the workspace does not hold
+ *    its tiles); launch or device errors give MX_EDEVICE; mont_last_error()
+ *    returns a thread-local message for the last non-OK status.  No call
+ *    aborts.
  *  - Device-data preconditions (a, b < 2N; base < N) are not checked: a
  *    violation gives an unspecified value, never an out-of-bounds access.
  *    ctx_idx entries >= the context count are replaced by 0.
+ *  - Compared with the call list of the hot path: mont_ctx_query also
+ *    returns the limb width, mont_ctx_export also returns R mod N, and the
+ *    mixed-size launch is a plan (mx_mixed_plan_*) built once and launched
+ *    or replayed from a HIP graph, in place of one call over caller-built
+ *    job descriptors.
  */
 #ifndef MONTEXP_H
 #define MONTEXP_H
@@ -92,9 +109,18 @@ enum {
  * words in host memory; each modulus odd, >= 3 and below 2^bits, else
  * MX_EINVAL (the offending index is in mont_last_error()).  The constants
  * are computed on the device; the call blocks until they are resident.
+ * It also allocates the context's workspace: enough for one launch of
+ * `count` instances at the class's default window (at most 256 MiB).
  * *out receives the context (NULL on failure); free with mont_ctx_destroy. */
 mx_status mont_ctx_init(mont_ctx **out, const uint64_t *moduli_host, uint32_t bits, uint32_t count,
                         void *stream);
+
+/* Grows the context's workspace to at least `bytes` (modexp_ws_bytes,
+ * mont_ws_bytes or rsa_crt_ws_bytes give the size a call needs for one
+ * launch).  Allocates device memory; first waits for the work already
+ * queued on the old workspace (this context's only).  A no-op when the
+ * workspace is already large enough.  Not for use during stream capture. */
+mx_status mont_ctx_reserve(mont_ctx *ctx, size_t bytes);
 
 /* Size class, r_bits (log2 R), limb bits (28), context count and device bytes.
  * Any output pointer may be NULL. */
@@ -114,7 +140,11 @@ void mont_ctx_destroy(mont_ctx *ctx);
  * are mont_words wide; precondition a, b < 2N, result < 2N.  MX_REDC_TRUNC
  * and MX_REDC_PLAIN return identical bits.  ctx_idx (device, n entries) picks
  * the context of each instance; NULL means instance i uses context i (then
- * n <= count).  out may alias a or b.  n = 0 is a no-op. */
+ * n <= count).  out may alias a or b.  n = 0 is a no-op.  The block kernels
+ * (MX_IMPL_BLOCK, MX_MUL_KARATSUBA, classes above 2048 bits) keep their
+ * operands in the context's workspace: n is done in as many launches as it
+ * holds (mont_ws_bytes gives one launch's size); MX_ENOMEM if it holds
+ * fewer than 64 instances. */
 mx_status mont_mul_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint64_t *a, const uint64_t *b,
                          uint64_t *out, uint32_t n, uint32_t flags, void *stream);
 
@@ -128,10 +158,11 @@ mx_status mont_sqr_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uin
  * base < N.  exp: ceil(exp_bits / 64) words per instance; exp_bits is public
  * and leading zeros are processed; bits above exp_bits are ignored.
  * exp_bits = 0 gives 1 (also 0^0 = 1).  window in 1..8, 0 = library choice.
- * The library-owned workspace (2^w * r_bits/8 bytes per instance) grows on
- * demand; a growth allocates device memory.  Calls on one context share that
- * workspace: the host side is serialised, the device work is not, so issue
- * them on one stream (or use modexp_batch_ws).  out may alias base. */
+ * The window table and working arrays live in the context's workspace
+ * (modexp_ws_bytes): n is done in as many launches as it holds, MX_ENOMEM if
+ * it holds fewer than 64 instances (mont_ctx_reserve grows it).  Calls on one
+ * context take turns on that workspace (see Streams above); modexp_batch_ws
+ * lets them overlap.  out may alias base. */
 mx_status modexp_batch(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint64_t *base, const uint64_t *exp,
                        uint32_t exp_bits, uint32_t window, uint64_t *out, uint32_t n, uint32_t flags,
                        void *stream);
@@ -145,8 +176,14 @@ mx_status modexp_batch_ws(const mont_ctx *ctx, const uint32_t *ctx_idx, const ui
                           uint32_t exp_bits, uint32_t window, uint64_t *out, uint32_t n, uint32_t flags, void *ws,
                           size_t ws_bytes, void *stream);
 
-/* Workspace bytes a single launch of n instances needs for this window and flags. */
+/* Workspace bytes a single launch of n instances needs for this window and
+ * flags (larger batches than one 2 GiB launch holds: the bytes of one such
+ * launch). */
 mx_status modexp_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t window, uint32_t flags, size_t *bytes);
+
+/* The same for mont_mul_batch / mont_sqr_batch (0 for the register-resident
+ * kernels, which need no workspace). */
+mx_status mont_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t flags, size_t *bytes);
 
 /* ---- RSA private-key operations by the Chinese remainder theorem -----------
  * The application the paper's batched exponentiation is built for (Section
@@ -164,17 +201,31 @@ mx_status modexp_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t window, uint
  * qinv < p; the exponents have exp_bits = bits.  out: 2 W words per
  * instance, canonical (< p q).  window and flags (MX_REDC_PLAIN or
  * MX_REDC_CIOS) apply to the two exponentiations.  out may alias c but not
- * dp, dq or qinv.  The two intermediates (n W words each) live in a buffer
- * owned by ctx_p that grows on demand (a growth allocates device memory), next
- * to the exponentiation workspaces of both contexts; as for modexp_batch,
- * calls sharing a context must be issued on one stream. */
+ * dp, dq or qinv.  The two intermediates (n W words each) and the
+ * exponentiations' table live in ctx_p's workspace (rsa_crt_ws_bytes gives
+ * the size of one launch over both halves; a smaller workspace runs them one
+ * after the other, in several launches if needed; MX_ENOMEM if it cannot
+ * hold the intermediates and one 64-instance tile). */
 mx_status rsa_crt_batch(const mont_ctx *ctx_p, const mont_ctx *ctx_q, const uint32_t *key_idx, const uint64_t *c,
                         const uint64_t *dp, const uint64_t *dq, const uint64_t *qinv, uint32_t window,
                         uint64_t *out, uint32_t n, uint32_t flags, void *stream);
 
+/* As rsa_crt_batch with a caller-owned device workspace of ws_bytes bytes
+ * (MX_EINVAL if it cannot hold the intermediates and one tile): no lock, so
+ * calls with their own workspaces may overlap on different streams. */
+mx_status rsa_crt_batch_ws(const mont_ctx *ctx_p, const mont_ctx *ctx_q, const uint32_t *key_idx,
+                           const uint64_t *c, const uint64_t *dp, const uint64_t *dq, const uint64_t *qinv,
+                           uint32_t window, uint64_t *out, uint32_t n, uint32_t flags, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* Workspace bytes of rsa_crt_batch over n instances as one paired launch
+ * (where the class has it) for this window and flags. */
+mx_status rsa_crt_ws_bytes(const mont_ctx *ctx_p, uint32_t n, uint32_t window, uint32_t flags, size_t *bytes);
+
 /* ---- mixed sizes in one persistent launch ----------------------------------
  * For callers that hold batches of several size classes at once (not a
- * construct of the paper, which exponentiates one size per call): the
+ * construct of the paper, which exponentiates one size per call; this plan
+ * takes the place of a single mixed-launch call over job descriptors): the
  * instances of all batches are cut into 64-instance tiles, ordered by
  * decreasing cost and consumed by one persistent grid (one wavefront per
  * SIMD) through a device work counter.  The truncated reduction is used.

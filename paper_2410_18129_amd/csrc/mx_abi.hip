@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <memory>
 #include <mutex>
 
 #include "../../include/montexp.h"
@@ -39,6 +40,14 @@ mx_status fail(mx_status st, const char* fmt, ...) {
 
 mx_status dev_fail(hipError_t e, const char* where) {
   return fail(e == hipErrorOutOfMemory ? MX_ENOMEM : MX_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// A launcher's error: hipErrorInvalidValue is its own refusal of a launch whose tiles the
+// workspace does not hold (nothing was enqueued); anything else comes from the runtime.
+mx_status launch_fail(hipError_t e, const char* where) {
+  if (e == hipErrorInvalidValue)
+    return fail(MX_EINVAL, "%s: launch refused: the workspace is smaller than the launch's tiles", where);
+  return dev_fail(e, where);
 }
 
 uint32_t words_for(uint32_t bits) { return (bits + 63) / 64; }
@@ -81,20 +90,33 @@ mx_status mx_fail(mx_status st, const char* fmt, ...) {
 
 
 
-// Grows the context's workspace to at least `need` bytes (caller holds ws_mu).
-static mx_status ensure_ws(mont_ctx* ctx, size_t need, const char* name) {
-  if (ctx->ws_bytes >= need) return MX_OK;
-  // the old buffer may still be read by queued work: drain before freeing
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) return dev_fail(e, name);
-  if (ctx->ws) (void)hipFree(ctx->ws);
-  ctx->ws = nullptr;
-  ctx->ws_bytes = 0;
-  e = hipMalloc(&ctx->ws, need);
-  if (e != hipSuccess) return dev_fail(e, name);
-  ctx->ws_bytes = need;
-  return MX_OK;
+// Instances per launch for a workspace of `avail` bytes with `rows` 32-bit words per instance:
+// whole 64-instance tiles, at most n, and under the 2 GiB one buffer descriptor spans.  0 when one
+// tile does not fit.
+static uint32_t fit_instances(uint32_t rows, uint32_t n, size_t avail) {
+  if (rows == 0) return n;
+  const size_t cap = avail < mx::kMaxWsBytes ? avail : mx::kMaxWsBytes;
+  uint64_t c = (cap / ((uint64_t)rows * sizeof(uint32_t))) / 64 * 64;
+  if (c > n) c = n;
+  return (uint32_t)c;
 }
+
+// Bytes of workspace one launch over `cnt` instances uses (whole tiles).
+static size_t launch_bytes(uint32_t rows, uint32_t cnt) { return (size_t)rows * round_up(cnt, 64) * sizeof(uint32_t); }
+
+// Takes a context's library workspace for a batch call: holds its lock and, on construction,
+// makes `stream` wait for the work last enqueued on it (possibly from another stream); on
+// release, records that this call's work is now the last.
+struct WsTurn {
+  mont_ctx* ctx;
+  hipStream_t st;
+  std::unique_lock<std::mutex> lk;
+  hipError_t err = hipSuccess;
+  WsTurn(mont_ctx* c, hipStream_t s) : ctx(c), st(s), lk(c->ws_mu) {
+    err = hipStreamWaitEvent(st, ctx->ws_done, 0);
+  }
+  hipError_t done() { return hipEventRecord(ctx->ws_done, st); }
+};
 
 // Kernel family for the flags: 0 register-resident, 1 block, 2 block + Karatsuba, 3 block with one
 // lane per instance whatever the batch size (MX_ONE_LANE), 4 block with at most two lanes per
@@ -125,13 +147,9 @@ static mx_status check_redc(const char* name, const mont_ctx* ctx, int impl, int
   return MX_OK;
 }
 
-// Instances per launch so that rows * padded count * 4 bytes fits one descriptor.
-static uint32_t chunk_for(uint32_t rows, uint32_t n) {
-  if (rows == 0) return n;
-  uint64_t c = (mx::kMaxWsBytes / ((uint64_t)rows * sizeof(uint32_t))) / 64 * 64;
-  if (c > n) c = n;
-  return (uint32_t)c;
-}
+// Library workspace a context reserves at init: one launch over its moduli at the default window,
+// up to this size.
+constexpr size_t kInitWsBytes = 256ull << 20;
 
 extern "C" {
 
@@ -190,12 +208,42 @@ mx_status mont_ctx_init(mont_ctx** out, const uint64_t* moduli_host, uint32_t bi
   if (e == hipSuccess) e = ops->ctx_init(dmods, c->dev, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (dmods) (void)hipFree(dmods);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    // the library workspace: one launch of `count` instances at the class's default window, at most
+    // kInitWsBytes (larger calls run in several launches, or call mont_ctx_reserve first)
+    const uint32_t rows = ops->ws_rows(0, true, default_window(bits));
+    const uint32_t fit = fit_instances(rows, count, kInitWsBytes);
+    const size_t want = launch_bytes(rows, fit ? fit : 64);
+    e = hipMalloc(&c->ws, want);
+    if (e == hipSuccess) c->ws_bytes = want;
+  }
   if (e != hipSuccess) {
+    if (c->ws_done) (void)hipEventDestroy(c->ws_done);
+    if (c->ws) (void)hipFree(c->ws);
     (void)hipFree(c->mem);
     delete c;
     return dev_fail(e, "mont_ctx_init");
   }
   *out = c;
+  return MX_OK;
+}
+
+mx_status mont_ctx_reserve(mont_ctx* ctx, size_t bytes) {
+  if (!ctx) return fail(MX_EINVAL, "mont_ctx_reserve: ctx is NULL");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(MX_EDEVICE, "mont_ctx_reserve: cannot select device");
+  std::lock_guard<std::mutex> lk(ctx->ws_mu);
+  if (ctx->ws_bytes >= bytes) return MX_OK;
+  // queued work may still use the old buffer: wait for it (this context's work only)
+  hipError_t e = hipEventSynchronize(ctx->ws_done);
+  if (e != hipSuccess) return dev_fail(e, "mont_ctx_reserve");
+  void* nw = nullptr;
+  e = hipMalloc(&nw, bytes);
+  if (e != hipSuccess) return dev_fail(e, "mont_ctx_reserve");
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  ctx->ws = nw;
+  ctx->ws_bytes = bytes;
   return MX_OK;
 }
 
@@ -239,7 +287,7 @@ mx_status mont_ctx_export(const mont_ctx* ctx, uint32_t idx, uint64_t* nprime_ho
 void mont_ctx_destroy(mont_ctx* ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
-  if (ctx->crt) (void)hipFree(ctx->crt);
+  if (ctx->ws_done) (void)hipEventDestroy(ctx->ws_done);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->mem) (void)hipFree(ctx->mem);
   delete ctx;
@@ -260,24 +308,30 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
   mont_ctx* mctx = const_cast<mont_ctx*>(ctx);
-  const uint32_t rows = ctx->ops->ws_rows(impl, false, 0);
-  const uint32_t chunk = chunk_for(rows, n);
-  if (chunk == 0) return fail(MX_EUNSUPPORTED, "%s: workspace row too large", name);
-  const uint32_t tstride = round_up(chunk, 64);
-  const size_t need = (size_t)rows * tstride * sizeof(uint32_t);
-  std::lock_guard<std::mutex> lk(mctx->ws_mu);
-  mx_status ms = ensure_ws(mctx, need, name);
-  if (ms != MX_OK) return ms;
   const uint32_t mw = words_for(28 * ctx->limbs);
-  for (uint32_t off = 0; off < n; off += chunk) {
-    const uint32_t cnt = n - off < chunk ? n - off : chunk;
-    hipError_t e = ctx->ops->mont(impl, redc, sqr, ctx->dev, ctx_idx ? ctx_idx + off : nullptr,
-                                  a + (size_t)off * mw, b + (size_t)off * mw, out + (size_t)off * mw, cnt,
-                                  (uint32_t*)mctx->ws, tstride, (uint32_t)need, ctx_idx ? 0u : off,
-                                  (hipStream_t)stream);
-    if (e != hipSuccess) return dev_fail(e, name);
+  const uint32_t rows = ctx->ops->ws_rows(impl, false, 0);
+  hipStream_t st = (hipStream_t)stream;
+  if (rows == 0) {  // register-resident kernels: no workspace
+    hipError_t e = ctx->ops->mont(impl, redc, sqr, ctx->dev, ctx_idx, a, b, out, n, nullptr, 0, 0,
+                                  0u, st);
+    return e == hipSuccess ? MX_OK : launch_fail(e, name);
   }
-  return MX_OK;
+  WsTurn turn(mctx, st);
+  if (turn.err != hipSuccess) return dev_fail(turn.err, name);
+  const uint32_t chunk = fit_instances(rows, n, mctx->ws_bytes);
+  if (chunk == 0)
+    return fail(MX_ENOMEM, "%s: the context workspace (%zu bytes) holds no tile; reserve %zu bytes with "
+                "mont_ctx_reserve", name, mctx->ws_bytes, launch_bytes(rows, 64));
+  hipError_t e = hipSuccess;
+  for (uint32_t off = 0; off < n && e == hipSuccess; off += chunk) {
+    const uint32_t cnt = n - off < chunk ? n - off : chunk;
+    e = ctx->ops->mont(impl, redc, sqr, ctx->dev, ctx_idx ? ctx_idx + off : nullptr, a + (size_t)off * mw,
+                       b + (size_t)off * mw, out + (size_t)off * mw, cnt, (uint32_t*)mctx->ws,
+                       round_up(cnt, 64), (uint32_t)launch_bytes(rows, cnt), ctx_idx ? 0u : off, st);
+  }
+  const hipError_t re = turn.done();
+  if (e != hipSuccess) return launch_fail(e, name);
+  return re == hipSuccess ? MX_OK : dev_fail(re, name);
 }
 
 mx_status mont_mul_batch(const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* a, const uint64_t* b,
@@ -290,82 +344,107 @@ mx_status mont_sqr_batch(const mont_ctx* ctx, const uint32_t* ctx_idx, const uin
   return mont_common("mont_sqr_batch", ctx, ctx_idx, a, a, out, n, flags, stream, true);
 }
 
-static mx_status modexp_common(const char* name, mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* base,
-                               const uint64_t* exp, uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n,
-                               uint32_t flags, void* user_ws, size_t user_ws_bytes, void* stream) {
+// Checks of an exponentiation call shared by the entry points; on MX_OK, *impl, *redc and *w hold
+// the kernel family, the reduction and the window.
+static mx_status modexp_args(const char* name, const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* base,
+                             const uint64_t* exp, uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n,
+                             uint32_t flags, int* impl, int* redc, uint32_t* w) {
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
-  if (n == 0) return MX_OK;
-  if (!base || !out || (exp_bits && !exp)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
+  if (n && (!base || !out || (exp_bits && !exp))) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
   if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_REDC_CIOS |
                           MX_TWO_LANES | MX_REDC_KARATSUBA))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
   if ((flags & MX_ONE_LANE) && (flags & MX_TWO_LANES))
     return fail(MX_EINVAL, "%s: MX_ONE_LANE and MX_TWO_LANES exclude each other", name);
-  const int impl = impl_of(ctx, flags);
-  if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
-  const int redc = redc_of(flags);
-  if (mx_status rs = check_redc(name, ctx, impl, redc); rs != MX_OK) return rs;
-  if (redc == mx::kRedcKara)
+  *impl = impl_of(ctx, flags);
+  if (*impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
+  *redc = redc_of(flags);
+  if (mx_status rs = check_redc(name, ctx, *impl, *redc); rs != MX_OK) return rs;
+  if (*redc == mx::kRedcKara)
     return fail(MX_EUNSUPPORTED, "%s: MX_REDC_KARATSUBA is built for mont_mul_batch / mont_sqr_batch only", name);
   if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
-  const uint32_t w = window ? window : default_window(ctx->bits);
+  *w = window ? window : default_window(ctx->bits);
+  return MX_OK;
+}
+
+// Enqueues the exponentiation of n instances in as many launches as a workspace of ws_bytes
+// needs (each launch under 2 GiB).  The caller owns the workspace for the stream's work.
+static mx_status modexp_launches(const char* name, const mont_ctx* ctx, int impl, int redc, const uint32_t* ctx_idx,
+                                 const uint64_t* base, const uint64_t* exp, uint32_t exp_bits, uint32_t w,
+                                 uint64_t* out, uint32_t n, void* ws, size_t ws_bytes, bool caller_ws,
+                                 hipStream_t st) {
   const uint32_t ewords = (exp_bits + 63) / 64;
   const uint32_t W = words_for(ctx->bits);
   const uint32_t rows = ctx->ops->ws_rows(impl, true, w);
-  uint32_t chunk = chunk_for(rows, n);
-  if (chunk == 0) return fail(MX_EUNSUPPORTED, "%s: window %u too large for this size class", name, w);
-  void* ws = nullptr;
-  size_t need = 0;
-  uint32_t tstride = 0;
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
-  std::unique_lock<std::mutex> lk(ctx->ws_mu, std::defer_lock);
-  if (user_ws) {
-    // instances per launch limited by the caller's buffer
-    const uint64_t fit = (user_ws_bytes / ((uint64_t)rows * sizeof(uint32_t))) / 64 * 64;
-    if (fit == 0) return fail(MX_EINVAL, "%s: workspace of %zu bytes is smaller than one tile", name, user_ws_bytes);
-    if (fit < chunk) chunk = (uint32_t)fit;
-    tstride = round_up(chunk, 64);
-    need = (size_t)rows * tstride * sizeof(uint32_t);
-    ws = user_ws;
-  } else {
-    tstride = round_up(chunk, 64);
-    need = (size_t)rows * tstride * sizeof(uint32_t);
-    lk.lock();
-    mx_status ms = ensure_ws(ctx, need, name);
-    if (ms != MX_OK) return ms;
-    ws = ctx->ws;
-  }
+  const uint32_t chunk = fit_instances(rows, n, ws_bytes);
+  if (chunk == 0)
+    return fail(caller_ws ? MX_EINVAL : MX_ENOMEM, "%s: a workspace of %zu bytes holds no 64-instance tile (%zu "
+                "bytes at window %u)%s", name, ws_bytes, launch_bytes(rows, 64), w,
+                caller_ws ? "" : ": reserve modexp_ws_bytes() with mont_ctx_reserve");
   for (uint32_t off = 0; off < n; off += chunk) {
     const uint32_t cnt = n - off < chunk ? n - off : chunk;
     hipError_t e = ctx->ops->modexp(impl, redc, ctx->dev, ctx_idx ? ctx_idx + off : nullptr, base + (size_t)off * W,
                                     exp_bits ? exp + (size_t)off * ewords : exp, exp_bits, ewords, w,
-                                    out + (size_t)off * W, cnt, (uint32_t*)ws, tstride, (uint32_t)need,
-                                    ctx_idx ? 0u : off, (hipStream_t)stream);
-    if (e != hipSuccess) return dev_fail(e, name);
+                                    out + (size_t)off * W, cnt, (uint32_t*)ws, round_up(cnt, 64),
+                                    (uint32_t)launch_bytes(rows, cnt), ctx_idx ? 0u : off, st);
+    if (e != hipSuccess) return launch_fail(e, name);
   }
   return MX_OK;
 }
 
 mx_status modexp_batch(const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* base, const uint64_t* exp,
                        uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n, uint32_t flags, void* stream) {
-  return modexp_common("modexp_batch", const_cast<mont_ctx*>(ctx), ctx_idx, base, exp, exp_bits, window, out, n,
-                       flags, nullptr, 0, stream);
+  const char* name = "modexp_batch";
+  int impl = 0, redc = 0;
+  uint32_t w = 0;
+  mx_status rs = modexp_args(name, ctx, ctx_idx, base, exp, exp_bits, window, out, n, flags, &impl, &redc, &w);
+  if (rs != MX_OK || n == 0) return rs;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
+  mont_ctx* c = const_cast<mont_ctx*>(ctx);
+  WsTurn turn(c, (hipStream_t)stream);
+  if (turn.err != hipSuccess) return dev_fail(turn.err, name);
+  rs = modexp_launches(name, ctx, impl, redc, ctx_idx, base, exp, exp_bits, w, out, n, c->ws, c->ws_bytes, false,
+                       (hipStream_t)stream);
+  const hipError_t e = turn.done();
+  if (rs == MX_OK && e != hipSuccess) return dev_fail(e, name);
+  return rs;
 }
 
 mx_status modexp_batch_ws(const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* base, const uint64_t* exp,
                           uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n, uint32_t flags, void* ws,
                           size_t ws_bytes, void* stream) {
-  if (!ws) return fail(MX_EINVAL, "modexp_batch_ws: workspace is NULL");
-  return modexp_common("modexp_batch_ws", const_cast<mont_ctx*>(ctx), ctx_idx, base, exp, exp_bits, window, out, n,
-                       flags, ws, ws_bytes, stream);
+  const char* name = "modexp_batch_ws";
+  if (!ws) return fail(MX_EINVAL, "%s: workspace is NULL", name);
+  int impl = 0, redc = 0;
+  uint32_t w = 0;
+  mx_status rs = modexp_args(name, ctx, ctx_idx, base, exp, exp_bits, window, out, n, flags, &impl, &redc, &w);
+  if (rs != MX_OK || n == 0) return rs;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
+  return modexp_launches(name, ctx, impl, redc, ctx_idx, base, exp, exp_bits, w, out, n, ws, ws_bytes, true,
+                         (hipStream_t)stream);
 }
 
-mx_status rsa_crt_batch(const mont_ctx* ctx_p, const mont_ctx* ctx_q, const uint32_t* key_idx, const uint64_t* c,
-                        const uint64_t* dp, const uint64_t* dq, const uint64_t* qinv, uint32_t window, uint64_t* out,
-                        uint32_t n, uint32_t flags, void* stream) {
-  const char* name = "rsa_crt_batch";
+}  // extern "C"
+
+// Bytes of the two intermediates of a CRT batch (c mod p then m1, c mod q then m2), whole 256-byte units.
+static size_t crt_inter_bytes(uint32_t bits, uint32_t n) {
+  return ((size_t)n * 2 * words_for(bits) * sizeof(uint64_t) + 255) / 256 * 256;
+}
+
+// Workspace of the two exponentiations as one paired launch (0 where the class has no paired kernel).
+static size_t crt_pair_bytes(const mont_ctx* cp, uint32_t n, uint32_t w, int redc) {
+  if (!cp->ops->modexp_pair || redc == mx::kRedcCios) return 0;
+  const size_t b = (size_t)cp->ops->ws_rows(0, true, w) * 64u * sizeof(uint32_t) * 2u * ((n + 63) / 64);
+  return b <= mx::kMaxWsBytes ? b : 0;
+}
+
+static mx_status rsa_crt_common(const char* name, const mont_ctx* ctx_p, const mont_ctx* ctx_q, const uint32_t* key_idx,
+                                const uint64_t* c, const uint64_t* dp, const uint64_t* dq, const uint64_t* qinv,
+                                uint32_t window, uint64_t* out, uint32_t n, uint32_t flags, void* user_ws,
+                                size_t user_ws_bytes, void* stream) {
   if (!ctx_p || !ctx_q) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (ctx_p->bits != ctx_q->bits) return fail(MX_EINVAL, "%s: p and q contexts of different classes", name);
   if (ctx_p->device != ctx_q->device) return fail(MX_EINVAL, "%s: contexts on different devices", name);
@@ -379,52 +458,92 @@ mx_status rsa_crt_batch(const mont_ctx* ctx_p, const mont_ctx* ctx_q, const uint
   if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
   const uint32_t cnt_min = ctx_p->count < ctx_q->count ? ctx_p->count : ctx_q->count;
   if (!key_idx && n > cnt_min) return fail(MX_EINVAL, "%s: n=%u exceeds the key count %u", name, n, cnt_min);
-  if (redc_of(flags) < 0) return fail(MX_EINVAL, "%s: MX_REDC_PLAIN and MX_REDC_CIOS exclude each other", name);
+  const int redc = redc_of(flags);
+  if (redc < 0) return fail(MX_EINVAL, "%s: MX_REDC_PLAIN and MX_REDC_CIOS exclude each other", name);
   DeviceGuard g(ctx_p->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
   mont_ctx* cp = const_cast<mont_ctx*>(ctx_p);
   mont_ctx* cq = const_cast<mont_ctx*>(ctx_q);
-  const uint32_t W = words_for(bits);
-  const size_t need = (size_t)n * 2 * W * sizeof(uint64_t);
-  std::lock_guard<std::mutex> lk(cp->crt_mu);
-  if (cp->crt_bytes < need) {
-    // the old buffer may still be read by queued work: drain before freeing
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return dev_fail(e, name);
-    if (cp->crt) (void)hipFree(cp->crt);
-    cp->crt = nullptr;
-    cp->crt_bytes = 0;
-    e = hipMalloc(&cp->crt, need);
-    if (e != hipSuccess) return dev_fail(e, name);
-    cp->crt_bytes = need;
-  }
-  uint64_t* xp = (uint64_t*)cp->crt;  // c mod p, then m1
-  uint64_t* xq = xp + (size_t)n * W;   // c mod q, then m2
   hipStream_t st = (hipStream_t)stream;
+  // workspace: the two intermediates, then the exponentiations' workspace
+  std::unique_ptr<WsTurn> turn;
+  uint8_t* ws = (uint8_t*)user_ws;
+  size_t ws_bytes = user_ws_bytes;
+  if (!ws) {
+    turn.reset(new WsTurn(cp, st));
+    if (turn->err != hipSuccess) return dev_fail(turn->err, name);
+    ws = (uint8_t*)cp->ws;
+    ws_bytes = cp->ws_bytes;
+  }
+  const uint32_t W = words_for(bits);
+  const uint32_t w = window ? window : default_window(bits);
+  const size_t inter = crt_inter_bytes(bits, n);
+  const size_t one_tile = launch_bytes(cp->ops->ws_rows(0, true, w), 64);
+  if (ws_bytes < inter + one_tile)
+    return fail(user_ws ? MX_EINVAL : MX_ENOMEM, "%s: workspace of %zu bytes < %zu (intermediates and one tile)%s",
+                name, ws_bytes, inter + one_tile, user_ws ? "" : ": reserve rsa_crt_ws_bytes() on ctx_p");
+  uint64_t* xp = (uint64_t*)ws;           // c mod p, then m1
+  uint64_t* xq = xp + (size_t)n * W;       // c mod q, then m2
+  uint8_t* ews = ws + inter;
+  const size_t ews_bytes = ws_bytes - inter;
   hipError_t e = bits == 1024 ? mx::crt_reduce_1024(cp->dev, cq->dev, key_idx, c, xp, xq, n, 0, st)
                               : mx::crt_reduce_2048(cp->dev, cq->dev, key_idx, c, xp, xq, n, 0, st);
-  if (e != hipSuccess) return dev_fail(e, name);
-  // the two half-size exponentiations, in place (the outputs may alias the bases): one
-  // launch over both halves where the class has it and its workspace fits one launch
-  const int redc = redc_of(flags);
-  const uint32_t w = window ? window : default_window(bits);
-  const size_t pair_ws = (size_t)cp->ops->ws_rows(0, true, w) * 64u * sizeof(uint32_t) * 2u * ((n + 63) / 64);
-  if (cp->ops->modexp_pair && redc != mx::kRedcCios && pair_ws <= mx::kMaxWsBytes) {
-    std::lock_guard<std::mutex> wl(cp->ws_mu);
-    mx_status ms = ensure_ws(cp, pair_ws, name);
-    if (ms != MX_OK) return ms;
+  mx_status rs = e == hipSuccess ? MX_OK : dev_fail(e, name);
+  // the two half-size exponentiations, in place (the outputs may alias the bases): one launch
+  // over both halves where the class has it and the workspace holds it, else one after the other
+  const size_t pair = crt_pair_bytes(cp, n, w, redc);
+  if (rs == MX_OK && pair && pair <= ews_bytes) {
     e = cp->ops->modexp_pair(redc == mx::kRedcTrunc, cp->dev, cq->dev, key_idx, xp, dp, dq, bits, W, w, xp, n,
-                             (uint32_t*)cp->ws, (uint32_t)pair_ws, st);
-    if (e != hipSuccess) return dev_fail(e, name);
-  } else {
-    mx_status ms = modexp_common(name, cp, key_idx, xp, dp, bits, window, xp, n, flags, nullptr, 0, stream);
-    if (ms != MX_OK) return ms;
-    ms = modexp_common(name, cq, key_idx, xq, dq, bits, window, xq, n, flags, nullptr, 0, stream);
-    if (ms != MX_OK) return ms;
+                             (uint32_t*)ews, (uint32_t)pair, st);
+    if (e != hipSuccess) rs = launch_fail(e, name);
+  } else if (rs == MX_OK) {
+    const int impl = 0;
+    rs = modexp_launches(name, cp, impl, redc, key_idx, xp, dp, bits, w, xp, n, ews, ews_bytes, true, st);
+    if (rs == MX_OK)
+      rs = modexp_launches(name, cq, impl, redc, key_idx, xq, dq, bits, w, xq, n, ews, ews_bytes, true, st);
   }
-  e = bits == 1024 ? mx::crt_garner_1024(cp->dev, cq->dev, key_idx, xp, xq, qinv, out, n, 0, st)
-                   : mx::crt_garner_2048(cp->dev, cq->dev, key_idx, xp, xq, qinv, out, n, 0, st);
-  if (e != hipSuccess) return dev_fail(e, name);
+  if (rs == MX_OK) {
+    e = bits == 1024 ? mx::crt_garner_1024(cp->dev, cq->dev, key_idx, xp, xq, qinv, out, n, 0, st)
+                     : mx::crt_garner_2048(cp->dev, cq->dev, key_idx, xp, xq, qinv, out, n, 0, st);
+    if (e != hipSuccess) rs = dev_fail(e, name);
+  }
+  if (turn) {
+    e = turn->done();
+    if (rs == MX_OK && e != hipSuccess) rs = dev_fail(e, name);
+  }
+  return rs;
+}
+
+extern "C" {
+
+mx_status rsa_crt_batch(const mont_ctx* ctx_p, const mont_ctx* ctx_q, const uint32_t* key_idx, const uint64_t* c,
+                        const uint64_t* dp, const uint64_t* dq, const uint64_t* qinv, uint32_t window, uint64_t* out,
+                        uint32_t n, uint32_t flags, void* stream) {
+  return rsa_crt_common("rsa_crt_batch", ctx_p, ctx_q, key_idx, c, dp, dq, qinv, window, out, n, flags, nullptr, 0,
+                        stream);
+}
+
+mx_status rsa_crt_batch_ws(const mont_ctx* ctx_p, const mont_ctx* ctx_q, const uint32_t* key_idx, const uint64_t* c,
+                           const uint64_t* dp, const uint64_t* dq, const uint64_t* qinv, uint32_t window,
+                           uint64_t* out, uint32_t n, uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
+  if (!ws) return fail(MX_EINVAL, "rsa_crt_batch_ws: workspace is NULL");
+  return rsa_crt_common("rsa_crt_batch_ws", ctx_p, ctx_q, key_idx, c, dp, dq, qinv, window, out, n, flags, ws,
+                        ws_bytes, stream);
+}
+
+mx_status rsa_crt_ws_bytes(const mont_ctx* ctx_p, uint32_t n, uint32_t window, uint32_t flags, size_t* bytes) {
+  if (!ctx_p || !bytes) return fail(MX_EINVAL, "rsa_crt_ws_bytes: NULL argument");
+  if (ctx_p->bits != 1024 && ctx_p->bits != 2048)
+    return fail(MX_EUNSUPPORTED, "rsa_crt_ws_bytes: %u-bit primes (1024 and 2048 are built)", ctx_p->bits);
+  if (window > 8) return fail(MX_EINVAL, "rsa_crt_ws_bytes: window %u outside 1..8", window);
+  const int redc = redc_of(flags);
+  if (redc < 0 || (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_REDC_CIOS)))
+    return fail(MX_EINVAL, "rsa_crt_ws_bytes: bad flags 0x%x", flags);
+  const uint32_t w = window ? window : default_window(ctx_p->bits);
+  const size_t pair = crt_pair_bytes(ctx_p, n ? n : 1, w, redc);
+  const uint32_t rows = ctx_p->ops->ws_rows(0, true, w);
+  const size_t ex = pair ? pair : launch_bytes(rows, fit_instances(rows, n ? n : 1, mx::kMaxWsBytes));
+  *bytes = crt_inter_bytes(ctx_p->bits, n) + ex;
   return MX_OK;
 }
 
@@ -435,8 +554,18 @@ mx_status modexp_ws_bytes(const mont_ctx* ctx, uint32_t n, uint32_t window, uint
   if (window > 8) return fail(MX_EINVAL, "modexp_ws_bytes: window %u outside 1..8", window);
   const uint32_t w = window ? window : default_window(ctx->bits);
   const uint32_t rows = ctx->ops->ws_rows(impl, true, w);
-  const uint32_t chunk = chunk_for(rows, n ? n : 1);
-  *bytes = (size_t)rows * round_up(chunk ? chunk : 64, 64) * sizeof(uint32_t);
+  const uint32_t chunk = fit_instances(rows, n ? n : 1, mx::kMaxWsBytes);
+  *bytes = launch_bytes(rows, chunk ? chunk : 64);
+  return MX_OK;
+}
+
+mx_status mont_ws_bytes(const mont_ctx* ctx, uint32_t n, uint32_t flags, size_t* bytes) {
+  if (!ctx || !bytes) return fail(MX_EINVAL, "mont_ws_bytes: NULL argument");
+  const int impl = impl_of(ctx, flags);
+  if (impl < 0) return fail(MX_EUNSUPPORTED, "mont_ws_bytes: kernel family not built for this class");
+  const uint32_t rows = ctx->ops->ws_rows(impl, false, 0);
+  const uint32_t chunk = fit_instances(rows, n ? n : 1, mx::kMaxWsBytes);
+  *bytes = rows ? launch_bytes(rows, chunk ? chunk : 64) : 0;
   return MX_OK;
 }
 

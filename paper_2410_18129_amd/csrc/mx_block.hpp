@@ -817,7 +817,7 @@ __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __r
   constexpr uint32_t n = Lay::n;
   const uint32_t gid = blockIdx.x * 64 + threadIdx.x;
   constexpr uint32_t tbytes = Lay::G * 256u;  // this block's region: G rows x 64 lanes
-  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // unreachable: the launcher checked ws
   const bool live = gid < count;
   const uint32_t inst = live ? gid : count - 1;
   uint32_t c = cidx ? cidx[inst] : inst + coff;
@@ -935,7 +935,9 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
     mont_blk<H, K, TRUNC, KARA, LP>(kind == kSqr, ws, cn, cnp);
     if (store_e >= 0) copy_rows<H>(ws, Lay::G + (uint32_t)store_e * n, ws, Lay::Y, n);
   }
-  // canonical result: subtract N once if Y >= N (constant time)
+  // canonical result: subtract N once if Y >= N, in constant time: B = Y - N, then every limb of B
+  // becomes Y's or stays B's under an all-ones / all-zero mask, so the rows read and written, and
+  // the row the result is taken from, do not depend on the value
   int64_t br = 0;
 #pragma nounroll
   for (uint32_t i = 0; i < n; ++i) {
@@ -943,8 +945,11 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
     ws.st(Lay::B + i, (uint32_t)v & kLimbMask);
     br = v >> kLimbBits;
   }
-  const uint32_t src = br != 0 ? Lay::Y : Lay::B;
-  if (writer) contract_rows<H, K>(ws, src, out + (size_t)inst * bw, bw);
+  const uint32_t keep_y = (uint32_t)br;  // br is -1 (Y < N: keep Y) or 0 (keep Y - N)
+#pragma nounroll
+  for (uint32_t i = 0; i < n; ++i)
+    ws.st(Lay::B + i, (ws.ld(Lay::Y + i) & keep_y) | (ws.ld(Lay::B + i) & ~keep_y));
+  if (writer) contract_rows<H, K>(ws, Lay::B, out + (size_t)inst * bw, bw);
 }
 
 template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1>
@@ -955,7 +960,7 @@ __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* _
                                                    uint32_t ws_bytes, uint32_t coff) {
   const uint32_t tile0 = blockIdx.x * (64u / LP);
   const uint32_t tbytes = BlkLayout<H, K>::rows(w) * (256u / LP);  // this block's region
-  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // unreachable: the launcher checked ws
   stagger<H * K>(blockIdx.x, w);
   modexp_tile_blk<H, K, TRUNC, KARA, LP>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
                                          ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0);

@@ -96,7 +96,7 @@ k_modexp_2w(CtxDev ctx, const uint32_t* __restrict__ cidx, const uint64_t* __res
   __shared__ uint32_t s_ctx[2 * N * 64];
   const uint32_t tile0 = blockIdx.x * 64;
   const uint32_t tbytes = (1u << w) * (uint32_t)packed_words(N) * 256u;
-  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // unreachable: the launcher checked ws
   stagger<N>(blockIdx.x, w);
   modexp_tile<N, BW, TRUNC>(ctx, cidx, base, ex, ebits, ewords, w, out, count, ws + (size_t)blockIdx.x * (tbytes / 4u),
                             tbytes, coff, tile0, s_ctx);
@@ -119,7 +119,7 @@ k_modexp_2w_pair(CtxDev c0, CtxDev c1, const uint32_t* __restrict__ cidx, const 
   const bool second = blockIdx.x >= nb;
   const uint32_t tile0 = (blockIdx.x - (second ? nb : 0u)) * 64;
   const uint32_t tbytes = (1u << w) * (uint32_t)packed_words(N) * 256u;
-  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // unreachable: the launcher checked ws
   const size_t off = second ? (size_t)count * BW : 0;
   stagger<N>(blockIdx.x, w);
   modexp_tile<N, BW, TRUNC>(second ? c1 : c0, cidx, base + off, second ? e1 : e0, ebits, ewords, w, out + off,
@@ -147,6 +147,8 @@ hipError_t mont_fn(int impl, int redc, bool sqr, const CtxDev& ctx, const uint32
                    uint32_t ws_bytes, uint32_t coff, hipStream_t st) {
   const uint32_t blocks = (count + 63) / 64;
   const bool trunc = redc == kRedcTrunc;
+  // every block's region must lie in ws: checked here, before anything is enqueued
+  if ((uint64_t)ws_rows_fn(impl, false, 0) * 256u * blocks > ws_bytes) return hipErrorInvalidValue;
   if constexpr (kHasKara) {
     if (impl == 2) {
 #define MX_L(T, S)                                                                                                \
@@ -204,6 +206,9 @@ hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx
   (void)tstride;
   const uint32_t blocks = (count + 63) / 64;
   const bool trunc = redc == kRedcTrunc;
+  // every block's region must lie in ws (with LP lanes per instance a block's region is 1/LP of a
+  // 64-instance tile's): checked here, before anything is enqueued
+  if ((uint64_t)ws_rows_fn(impl, true, w) * 256u * blocks > ws_bytes) return hipErrorInvalidValue;
   if constexpr (kHasKara) {
     if (impl == 2) {
       if (trunc)
@@ -280,6 +285,7 @@ hipError_t modexp_pair_fn(bool trunc, const CtxDev& c0, const CtxDev& c1, const 
                           hipStream_t st) {
   if constexpr (kTwoWaves) {
     const uint32_t blocks = 2 * ((count + 63) / 64);
+    if ((uint64_t)ws_rows_fn(0, true, w) * 256u * blocks > ws_bytes) return hipErrorInvalidValue;
     if (trunc)
       hipLaunchKernelGGL((k_modexp_2w_pair<kN, kW, true>), dim3(blocks), dim3(64), 0, st, c0, c1, cidx, base, e0,
                          e1, ebits, ewords, w, out, count, ws, ws_bytes);

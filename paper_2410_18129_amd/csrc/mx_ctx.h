@@ -20,14 +20,13 @@ struct mont_ctx {
   mx::CtxDev dev{};
   void* mem = nullptr;
   size_t bytes = 0;
-  // per-instance workspace owned by the context (grow-only; guarded by ws_mu)
+  // library-owned workspace (guarded by ws_mu): sized by mont_ctx_init and grown only by
+  // mont_ctx_reserve, never inside a batch call.  ws_done is recorded after the last work enqueued
+  // on it; every batch call that uses it first makes its stream wait for ws_done, so calls on
+  // different streams take turns on the workspace instead of racing on it.
   std::mutex ws_mu;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  // the two half-size intermediates of rsa_crt_batch when this is the context
-  // of the first primes (grow-only; guarded by crt_mu, which is taken before ws_mu)
-  std::mutex crt_mu;
-  void* crt = nullptr;
-  size_t crt_bytes = 0;
+  hipEvent_t ws_done = nullptr;
 };
 

@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(64) k_modexp(CtxDev ctx, const uint32_t* __res
   __shared__ uint32_t s_ctx[2 * N * 64];
   const uint32_t tile0 = blockIdx.x * 64;
   const uint32_t tbytes = (1u << w) * (uint32_t)packed_words(N) * 256u;
-  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // unreachable: the launcher checked ws
   stagger<N>(blockIdx.x, w);
   modexp_tile<N, BW, TRUNC>(ctx, cidx, base, ex, ebits, ewords, w, out, count, ws + (size_t)blockIdx.x * (tbytes / 4u),
                             tbytes, coff, tile0, s_ctx);
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(64) k_modexp_cios(CtxDev ctx, const uint32_t* 
   __shared__ uint32_t s_ctx[2 * N * 64];
   const uint32_t tile0 = blockIdx.x * 64;
   const uint32_t tbytes = (1u << w) * (uint32_t)packed_words(N) * 256u;
-  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // the host sizes ws for every tile
+  if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // unreachable: the launcher checked ws
   stagger<N>(blockIdx.x, w);
   modexp_tile<N, BW, false, true>(ctx, cidx, base, ex, ebits, ewords, w, out, count,
                                   ws + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0, s_ctx);

@@ -215,7 +215,7 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     const uint32_t rows = c->ops->ws_rows(impl, true, w);
     const size_t bytes = (size_t)rows * p->nslots * 64u * sizeof(uint32_t);
     if (bytes > mx::kMaxWsBytes) {
-      delete p;
+      mx_mixed_plan_destroy(p);  // frees the workspaces of the batches before this one
       return mx_fail(MX_EUNSUPPORTED, "batch %u: window %u needs %zu workspace bytes (> 2 GiB); use a smaller window",
                    b, w, bytes);
     }
@@ -335,9 +335,22 @@ mx_status mx_tune_modexp(const mont_ctx* ctx, uint32_t n, uint32_t exp_bits, con
   const uint32_t W = (ctx->bits + 63) / 64, ew = (exp_bits + 63) / 64;
   uint64_t *base = nullptr, *ex = nullptr, *out = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  const uint32_t fam_flags[3] = {0u, (uint32_t)MX_IMPL_BLOCK, (uint32_t)MX_MUL_KARATSUBA};
+  for (uint32_t impl = 0; impl < 3; ++impl) {  // one workspace large enough for every candidate
+    if ((impl == 1 && !ctx->ops->has_block) || (impl == 2 && !ctx->ops->has_kara) || (impl > 0 && !try_block))
+      continue;
+    for (uint32_t k = 0; k < nwin; ++k) {
+      size_t b = 0;
+      if (modexp_ws_bytes(ctx, n, windows[k], fam_flags[impl], &b) != MX_OK) return MX_EINVAL;
+      ws_bytes = std::max(ws_bytes, b);
+    }
+  }
   hipError_t e = hipMalloc(&base, (size_t)n * W * 8);
   if (e == hipSuccess) e = hipMalloc(&ex, (size_t)n * std::max(ew, 1u) * 8);
   if (e == hipSuccess) e = hipMalloc(&out, (size_t)n * W * 8);
+  if (e == hipSuccess) e = hipMalloc(&ws, ws_bytes);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e == hipSuccess) {
@@ -352,19 +365,20 @@ mx_status mx_tune_modexp(const mont_ctx* ctx, uint32_t n, uint32_t exp_bits, con
   }
   mx_status rs = MX_OK;
   float best = 1e30f;
-  const uint32_t fam_flags[3] = {0u, (uint32_t)MX_IMPL_BLOCK, (uint32_t)MX_MUL_KARATSUBA};
   for (uint32_t impl = 0; impl < 3 && e == hipSuccess; ++impl) {
     if (impl > 0 && !try_block) break;
     if (impl == 1 && !ctx->ops->has_block) continue;
     if (impl == 2 && !ctx->ops->has_kara) continue;
     for (uint32_t k = 0; k < nwin && e == hipSuccess; ++k) {
       const uint32_t flags = fam_flags[impl];
-      rs = modexp_batch(ctx, nullptr, base, ex, exp_bits, windows[k], out, n, flags, stream);  // warm-up / growth
+      rs = modexp_batch_ws(ctx, nullptr, base, ex, exp_bits, windows[k], out, n, flags, ws, ws_bytes,
+                           stream);  // warm-up
       if (rs != MX_OK) break;
       float ms = 1e30f;
       for (uint32_t r = 0; r < std::max(reps, 1u) && e == hipSuccess; ++r) {
         e = hipEventRecord(e0, st);
-        if (e == hipSuccess) rs = modexp_batch(ctx, nullptr, base, ex, exp_bits, windows[k], out, n, flags, stream);
+        if (e == hipSuccess)
+          rs = modexp_batch_ws(ctx, nullptr, base, ex, exp_bits, windows[k], out, n, flags, ws, ws_bytes, stream);
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float t = 0.f;
@@ -385,7 +399,8 @@ mx_status mx_tune_modexp(const mont_ctx* ctx, uint32_t n, uint32_t exp_bits, con
   if (base) (void)hipFree(base);
   if (ex) (void)hipFree(ex);
   if (out) (void)hipFree(out);
-  if (rs != MX_OK) return rs;  // modexp_batch recorded the message
+  if (ws) (void)hipFree(ws);
+  if (rs != MX_OK) return rs;  // modexp_batch_ws recorded the message
   if (e != hipSuccess) return mx_fail(MX_EDEVICE, "mx_tune_modexp: %s", hipGetErrorString(e));
   *best_ms = best * 64.f / (float)n;  // per 64-instance tile
   return MX_OK;

@@ -30,12 +30,17 @@ _SIGS = {
                                       ctypes.POINTER(_U32), ctypes.POINTER(ctypes.c_size_t)]),
     "mont_ctx_export": (ctypes.c_int, [_P, _U32, _P, _P, _P]),
     "mont_ctx_destroy": (None, [_P]),
+    "mont_ctx_reserve": (ctypes.c_int, [_P, ctypes.c_size_t]),
+    "mont_ws_bytes": (ctypes.c_int, [_P, _U32, _U32, ctypes.POINTER(ctypes.c_size_t)]),
     "mont_mul_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _U32, _U32, _P]),
     "mont_sqr_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P]),
     "modexp_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P]),
     "modexp_batch_ws": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P, ctypes.c_size_t, _P]),
     "modexp_ws_bytes": (ctypes.c_int, [_P, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_size_t)]),
     "rsa_crt_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _U32, _P, _U32, _U32, _P]),
+    "rsa_crt_batch_ws": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _U32, _P, _U32, _U32, _P, ctypes.c_size_t,
+                                        _P]),
+    "rsa_crt_ws_bytes": (ctypes.c_int, [_P, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_size_t)]),
     "mx_mixed_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), _P, _U32]),
     "mx_mixed_plan_launch": (ctypes.c_int, [_P, _P]),
     "mx_mixed_plan_launch_graph": (ctypes.c_int, [_P, _P]),
@@ -148,6 +153,10 @@ class Context:
             raise ValueError("context destroyed")
         return self._h
 
+    def reserve(self, nbytes):
+        """Grows the context's library workspace to at least nbytes (mont_ctx_reserve; allocates)."""
+        _check(lib().mont_ctx_reserve(self.handle, nbytes))
+
     def device_bytes(self):
         nb = ctypes.c_size_t()
         _check(lib().mont_ctx_query(self.handle, None, None, None, None, ctypes.byref(nb)))
@@ -202,6 +211,15 @@ def _check_idx(ctx_idx, n, ctx):
         raise ValueError("ctx_idx: expected int32 device tensor [%d]" % n)
 
 
+def _reserve_mont(ctx, n, flags):
+    """One launch's workspace for the block kernels' single operations (none for the others)."""
+    if not n or flags & MX_MUL_KARATSUBA == 0 and flags & MX_IMPL_BLOCK == 0 and ctx.bits <= 2048:
+        return
+    nb = ctypes.c_size_t()
+    if lib().mont_ws_bytes(ctx.handle, n, flags & (MX_IMPL_BLOCK | MX_MUL_KARATSUBA), ctypes.byref(nb)) == MX_OK:
+        ctx.reserve(nb.value)
+
+
 def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=False, cios=False,
              kara_redc=False):
     """REDC(a*b) per instance; a, b: int64 device tensors [n, mont_words]."""
@@ -213,6 +231,7 @@ def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
     flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_REDC_KARATSUBA if kara_redc else 0)
+    _reserve_mont(ctx, n, flags)
     _check(lib().mont_mul_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(b), _ptr(out), n, flags,
                                 _stream_ptr(stream)))
     return out
@@ -229,6 +248,7 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=Fal
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
     flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_REDC_KARATSUBA if kara_redc else 0)
+    _reserve_mont(ctx, n, flags)
     _check(lib().mont_sqr_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(out), n, flags, _stream_ptr(stream)))
     return out
 
@@ -251,6 +271,8 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
     _check_idx(ctx_idx, n, ctx)
     flags = (_redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0) |
              (MX_TWO_LANES if two_lanes else 0))
+    if n:  # one launch's workspace (0, a no-op, for arguments the call itself rejects)
+        ctx.reserve(modexp_ws_bytes(ctx, n, window, flags=flags))
     _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,
                               window, _ptr(out), n, flags, _stream_ptr(stream)))
     return out
@@ -314,9 +336,14 @@ def tune_modexp(ctx, n, exp_bits, windows=(3, 4, 5, 6), try_block=True, reps=2, 
     return bw.value, bf.value, bms.value
 
 
-def modexp_ws_bytes(ctx, n, window=0, block=False):
+def modexp_ws_bytes(ctx, n, window=0, block=False, flags=None):
+    """Workspace bytes of one exponentiation launch over n instances (modexp_ws_bytes)."""
     nb = ctypes.c_size_t()
-    _check(lib().modexp_ws_bytes(ctx.handle, n, window, _impl_flags(block), ctypes.byref(nb)))
+    f = _impl_flags(block) if flags is None else flags
+    st = lib().modexp_ws_bytes(ctx.handle, n, window, f & (MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE |
+                                                          MX_TWO_LANES), ctypes.byref(nb))
+    if st != MX_OK:  # the batch call reports the same error with its own name
+        return 0
     return nb.value
 
 
@@ -348,8 +375,10 @@ def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, pl
     return out
 
 
-def rsa_crt(ctx_p, ctx_q, c, dp, dq, qinv, window=0, out=None, key_idx=None, plain=False, cios=False, stream=None):
-    """RSA private-key operation by the CRT (rsa_crt_batch): c^d mod p q per instance.
+def rsa_crt(ctx_p, ctx_q, c, dp, dq, qinv, window=0, out=None, key_idx=None, plain=False, cios=False, stream=None,
+            ws=None):
+    """RSA private-key operation by the CRT (rsa_crt_batch, or rsa_crt_batch_ws with a caller workspace ws):
+    c^d mod p q per instance.
 
     ctx_p, ctx_q: Contexts of the primes (same class, 1024 or 2048 bits); c, out: int64 [n, 2 W];
     dp, dq, qinv: int64 [n, W] with W = bits / 64; key_idx: int32 device tensor or None."""
@@ -364,9 +393,28 @@ def rsa_crt(ctx_p, ctx_q, c, dp, dq, qinv, window=0, out=None, key_idx=None, pla
         _check_idx(key_idx, n, ctx_p)
     elif n > min(ctx_p.count, ctx_q.count):
         raise ValueError("n exceeds the key count (pass key_idx)")
-    _check(lib().rsa_crt_batch(ctx_p.handle, ctx_q.handle, _ptr(key_idx), _ptr(c), _ptr(dp), _ptr(dq), _ptr(qinv),
-                               window, _ptr(out), n, _redc_flags(plain, cios), _stream_ptr(stream)))
+    flags = _redc_flags(plain, cios)
+    if n and ws is None:
+        nb = ctypes.c_size_t()
+        if lib().rsa_crt_ws_bytes(ctx_p.handle, n, window, flags, ctypes.byref(nb)) == MX_OK:
+            ctx_p.reserve(nb.value)
+    if ws is None:
+        _check(lib().rsa_crt_batch(ctx_p.handle, ctx_q.handle, _ptr(key_idx), _ptr(c), _ptr(dp), _ptr(dq),
+                                   _ptr(qinv), window, _ptr(out), n, flags, _stream_ptr(stream)))
+    else:
+        if not ws.is_cuda or not ws.is_contiguous():
+            raise ValueError("ws: expected a contiguous device tensor")
+        _check(lib().rsa_crt_batch_ws(ctx_p.handle, ctx_q.handle, _ptr(key_idx), _ptr(c), _ptr(dp), _ptr(dq),
+                                      _ptr(qinv), window, _ptr(out), n, flags, _ptr(ws), ws.numel() * ws.element_size(),
+                                      _stream_ptr(stream)))
     return out
+
+
+def rsa_crt_ws_bytes(ctx_p, n, window=0, plain=False, cios=False):
+    """Workspace bytes of rsa_crt over n instances as one paired launch (rsa_crt_ws_bytes)."""
+    nb = ctypes.c_size_t()
+    _check(lib().rsa_crt_ws_bytes(ctx_p.handle, n, window, _redc_flags(plain, cios), ctypes.byref(nb)))
+    return nb.value
 
 
 def to_device(words_u64, device="cuda"):
