@@ -176,6 +176,20 @@ mx_status modexp_batch_ws(const mont_ctx *ctx, const uint32_t *ctx_idx, const ui
                           uint32_t exp_bits, uint32_t window, uint64_t *out, uint32_t n, uint32_t flags, void *ws,
                           size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): modexp_batch with
+ * its workspace in a fixed array of 64 MiB that the library holds on each GPU
+ * it runs on until the process ends; the call itself allocates nothing.  The
+ * batch runs in one launch: MX_EINVAL, before anything is enqueued, if its
+ * workspace (modexp_ws_bytes) exceeds 64 MiB -- at window 5, 8064 instances
+ * of 2048 bits, 15872 of 1024 bits.  Every call on one GPU uses that GPU's
+ * array, whatever the context or stream: calls that overlap on the device
+ * race on it, so issue them on one stream (or order their streams).  The
+ * array's address is looked up when the first context is made on a device. */
+mx_status modexp_batch_noalloc(const mont_ctx *ctx, const uint32_t *ctx_idx, const uint64_t *base,
+                               const uint64_t *exp, uint32_t exp_bits, uint32_t window, uint64_t *out, uint32_t n,
+                               uint32_t flags, void *stream);
+
 /* Workspace bytes a single launch of n instances needs for this window and
  * flags (larger batches than one 2 GiB launch holds: the bytes of one such
  * launch). */

@@ -13,6 +13,16 @@
 #include "mx_internal.h"
 #include "mx_ctx.h"
 
+// ---- scratch of the allocation-free exponentiation (modexp_batch_noalloc) ----------------------
+// The entry point keeps its window table and working arrays in this file-scope device array instead
+// of a workspace that it allocates.  Each GPU the library runs on holds its own copy, at its own
+// address, until the process ends.  In host code the array's name is only a host-side stand-in for
+// the symbol, never a device address: the address of a device's copy comes from
+// hipGetSymbolAddress, looked up once per device, with that device current, by the first
+// mont_ctx_init on it, and only that address is passed to kernels.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
 namespace mx {
 // CRT-RSA steps around the two half-size exponentiations (mx_crt.hip, one object per prime class)
 #define MX_DECL_CRT(B)                                                                                                \
@@ -40,6 +50,34 @@ mx_status fail(mx_status st, const char* fmt, ...) {
 
 mx_status dev_fail(hipError_t e, const char* where) {
   return fail(e == hipErrorOutOfMemory ? MX_ENOMEM : MX_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Per-device addresses of `scratch` (see its definition above).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Looks up the current device's copy of `scratch` (the current device is `dev`), once per device.
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[dev] = e;
+  if (e == hipSuccess && p) g_scratch_ptr[dev] = p;
+}
+
+// The device address of `dev`'s copy of `scratch` (nullptr before its lookup or if it failed).
+void* scratch_of(int dev, hipError_t* err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
 }
 
 // A launcher's error: hipErrorInvalidValue is its own refusal of a launch whose tiles the
@@ -180,6 +218,7 @@ mx_status mont_ctx_init(mont_ctx** out, const uint64_t* moduli_host, uint32_t bi
     delete c;
     return fail(MX_EDEVICE, "mont_ctx_init: no HIP device");
   }
+  scratch_setup(c->device);  // this device's copy of the allocation-free entry point's scratch
   c->ops = ops;
   c->bits = bits;
   c->limbs = (uint32_t)limbs;
@@ -424,6 +463,32 @@ mx_status modexp_batch_ws(const mont_ctx* ctx, const uint32_t* ctx_idx, const ui
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
   return modexp_launches(name, ctx, impl, redc, ctx_idx, base, exp, exp_bits, w, out, n, ws, ws_bytes, true,
+                         (hipStream_t)stream);
+}
+
+mx_status modexp_batch_noalloc(const mont_ctx* ctx, const uint32_t* ctx_idx, const uint64_t* base,
+                               const uint64_t* exp, uint32_t exp_bits, uint32_t window, uint64_t* out, uint32_t n,
+                               uint32_t flags, void* stream) {
+  const char* name = "modexp_batch_noalloc";
+  int impl = 0, redc = 0;
+  uint32_t w = 0;
+  mx_status rs = modexp_args(name, ctx, ctx_idx, base, exp, exp_bits, window, out, n, flags, &impl, &redc, &w);
+  if (rs != MX_OK || n == 0) return rs;
+  const uint32_t rows = ctx->ops->ws_rows(impl, true, w);
+  const size_t need = launch_bytes(rows, n);
+  if (need > kScratchBytes)
+    return fail(MX_EINVAL, "%s: %u instances at window %u need %zu bytes of scratch; the maximum is %zu bytes "
+                "(%u instances): split the batch", name, n, w, need, kScratchBytes,
+                fit_instances(rows, 0xFFFFFFFFu, kScratchBytes));
+  hipError_t serr = hipSuccess;
+  void* ptr = scratch_of(ctx->device, &serr);
+  if (!ptr)
+    return fail(MX_EDEVICE, "%s: no scratch address for device %d: %s", name, ctx->device, hipGetErrorString(serr));
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
+  // one launch (need <= kScratchBytes < 2 GiB); every row a kernel reads it has written first in the
+  // same launch, so nothing in the scratch has to start at zero
+  return modexp_launches(name, ctx, impl, redc, ctx_idx, base, exp, exp_bits, w, out, n, ptr, kScratchBytes, true,
                          (hipStream_t)stream);
 }
 

@@ -35,6 +35,7 @@ _SIGS = {
     "mont_mul_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _U32, _U32, _P]),
     "mont_sqr_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P]),
     "modexp_batch": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P]),
+    "modexp_batch_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P]),
     "modexp_batch_ws": (ctypes.c_int, [_P, _P, _P, _P, _U32, _U32, _P, _U32, _U32, _P, ctypes.c_size_t, _P]),
     "modexp_ws_bytes": (ctypes.c_int, [_P, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_size_t)]),
     "rsa_crt_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _U32, _P, _U32, _U32, _P]),
