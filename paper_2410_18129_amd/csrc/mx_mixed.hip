@@ -89,8 +89,12 @@ __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
                                      mb.count, tw, tb, 0u, tile0);
         break;
       case kF3072B:
-        modexp_tile_blk<37, 3, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 48u, mb.out,
-                                     mb.count, tw, tb, 0u, tile0);
+        if (mb.lanes == 2)
+          modexp_tile_blk<37, 3, true, false, 2>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 48u,
+                                                 mb.out, mb.count, tw, tb, 0u, tile0);
+        else
+          modexp_tile_blk<37, 3, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 48u, mb.out,
+                                       mb.count, tw, tb, 0u, tile0);
         break;
       case kF2048K:
         modexp_tile_blk<37, 2, true, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 32u, mb.out,
@@ -100,7 +104,7 @@ __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
         modexp_tile_blk<37, 4, true, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u, mb.out,
                                            mb.count, tw, tb, 0u, tile0);
         break;
-      default:  // 4096 bits, schoolbook: two lanes per instance (these tiles bound the launch's length)
+      default:  // 4096 bits, schoolbook
         if (mb.lanes == 2)
           modexp_tile_blk<37, 4, true, false, 2>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u,
                                                  mb.out, mb.count, tw, tb, 0u, tile0);
@@ -130,6 +134,17 @@ __global__ void k_fill(uint64_t* p, uint32_t rows, uint32_t words, uint32_t topb
 }  // namespace mx
 
 namespace {
+
+// Lanes per instance of a batch: MX_ONE_LANE or MX_TWO_LANES where the family has both (the block
+// schoolbook kernels of 3072 and 4096 bits), else the default: two for 4096-bit schoolbook tiles (the
+// longest, which otherwise bound the launch), one for the rest.  0 if the flags ask for what the
+// family does not have.
+uint32_t lanes_of(uint32_t fam, uint32_t flags) {
+  const bool two_ok = fam == mx::kF3072B || fam == mx::kF4096B;
+  if (flags & MX_TWO_LANES) return two_ok ? 2u : 0u;
+  if (flags & MX_ONE_LANE) return 1u;
+  return fam == mx::kF4096B ? 2u : 1u;
+}
 
 bool family_of(const mont_ctx* c, uint32_t flags, uint32_t* fam) {
   const bool blk = (flags & MX_IMPL_BLOCK) != 0, kara = (flags & MX_MUL_KARATSUBA) != 0;
@@ -180,14 +195,19 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     const mx_batch_desc& d = batches[b];
     if (!d.ctx) return mx_fail(MX_EINVAL, "batch %u: ctx is NULL", b);
     if (d.ctx->device != dev) return mx_fail(MX_EINVAL, "batch %u: context lives on another device", b);
-    if (d.flags & ~(uint32_t)(MX_IMPL_BLOCK | MX_MUL_KARATSUBA))
+    if (d.flags & ~(uint32_t)(MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_TWO_LANES))
       return mx_fail(MX_EUNSUPPORTED, "batch %u: the mixed launch runs the truncated reduction only", b);
+    if ((d.flags & MX_ONE_LANE) && (d.flags & MX_TWO_LANES))
+      return mx_fail(MX_EINVAL, "batch %u: MX_ONE_LANE and MX_TWO_LANES exclude each other", b);
     if (!family_of(d.ctx, d.flags, &fam[b]))
       return mx_fail(MX_EUNSUPPORTED, "batch %u: %u-bit class not in the mixed launch", b, d.ctx->bits);
+    if (lanes_of(fam[b], d.flags) == 0)
+      return mx_fail(MX_EUNSUPPORTED, "batch %u: two lanes per instance exist for the 3072- and 4096-bit "
+                     "schoolbook tiles only", b);
     if (d.n && (!d.base || !d.out || (d.exp_bits && !d.exp))) return mx_fail(MX_EINVAL, "batch %u: NULL pointer", b);
     if (!d.ctx_idx && d.n > d.ctx->count) return mx_fail(MX_EINVAL, "batch %u: n exceeds the context count", b);
     if (d.window > 8) return mx_fail(MX_EINVAL, "batch %u: window outside 1..8", b);
-    const uint32_t per_tile = fam[b] == mx::kF4096B ? 32u : 64u;  // two lanes per 4096-bit instance
+    const uint32_t per_tile = 64u / lanes_of(fam[b], d.flags);
     total_tiles += (d.n + per_tile - 1) / per_tile;
   }
   if (total_tiles >= (1u << 28)) return mx_fail(MX_EINVAL, "mx_mixed_plan_create: too many tiles");
@@ -233,9 +253,9 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     mb.w = w;
     mb.family = fam[b];
     mb.rows = rows;
-    // the longest tiles (4096-bit schoolbook) run two lanes per instance: their tile
+    // by default the longest tiles (4096-bit schoolbook) run two lanes per instance: their tile
     // takes about 0.8 of the one-lane time, so the launch is not bound by them
-    mb.lanes = fam[b] == mx::kF4096B ? 2u : 1u;
+    mb.lanes = lanes_of(fam[b], d.flags);
     const uint32_t per_tile = 64u / mb.lanes;
     const float est = (float)c->limbs * c->limbs * (float)(d.exp_bits ? d.exp_bits : 1) * (mb.lanes == 2 ? 0.8f : 1.f);
     const float cost = d.tile_cost > 0.f ? d.tile_cost : est;

@@ -46,7 +46,9 @@ def stop():
 
 
 def submit(key, jobs):
-    """Queues oracle.modexp(a, e, N, ebits) for every (a, e, N, ebits) in jobs under `key`."""
+    """Queues oracle.modexp(a, e, N, ebits) for every (a, e, N, ebits) in jobs under `key` (once per key)."""
+    if key in _pending or key in _done:
+        return
     jobs = list(jobs)
     if _pool is None:
         _pending[key] = (jobs, None)

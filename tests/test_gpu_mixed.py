@@ -132,7 +132,8 @@ def _submit_plan():
         oracle_pool.submit(("plan", bits), _plan_jobs(bits))
 
 
-ORACLE_JOBS = {"test_mixed_plan_matches_single_class_and_oracle": _submit_plan}
+ORACLE_JOBS = {"test_mixed_plan_matches_single_class_and_oracle": _submit_plan,
+               "test_autotuned_plan_matches_single_class_and_oracle": _submit_plan}
 
 
 def _mixed_inputs(mx, counts, k=13):
@@ -210,13 +211,70 @@ def test_mixed_plan_rejects_bad_batches(mx):
     ctx.close()
 
 
-def test_autotuner_picks_a_candidate(mx, tmp_path):
+def test_autotuner_measures_and_caches_tile_times(mx, tmp_path):
     from paper_2410_18129_amd import autotune
-    plans = autotune.plan_for([1024], path=str(tmp_path / "cache.json"), n=512)
-    p = plans[1024]
-    assert p["window"] in autotune.CANDIDATES[1024] and p["ms_per_tile"] > 0
-    again = autotune.plan_for([1024], path=str(tmp_path / "cache.json"), n=512)  # cached, no re-measure
-    assert again == plans
+    cache = str(tmp_path / "cache.json")
+    t = autotune.tile_times([1024], path=cache, waves=16, reps=1)
+    assert set(t[1024]) == {autotune._key(w, f) for w, f in autotune.CANDIDATES[1024]}
+    assert all(v > 0 for v in t[1024].values())
+    assert autotune.tile_times([1024], path=cache, waves=16) == t  # cached, no re-measure
+
+
+def test_autotuned_plan_matches_single_class_and_oracle(mx, tmp_path):
+    """A plan built from the tuner's choice (window, family, lanes per class) gives what single-class launches
+    with the same window and family give, and the oracle's values."""
+    import torch
+    from paper_2410_18129_amd import autotune
+    counts = {1024: 130, 2048: 70, 3072: 65, 4096: 71}
+    waves = 32
+    # two candidates per large class keep the test short: one and two lanes per instance
+    cands = {1024: [(3, 0), (4, 0)], 2048: [(3, 0), (3, mx.MX_IMPL_BLOCK)],
+             3072: [(4, mx.MX_IMPL_BLOCK | mx.MX_ONE_LANE), (4, mx.MX_IMPL_BLOCK | mx.MX_TWO_LANES)],
+             4096: [(4, mx.MX_IMPL_BLOCK | mx.MX_ONE_LANE), (4, mx.MX_IMPL_BLOCK | mx.MX_TWO_LANES)]}
+    times = {b: autotune.measure_class(b, waves=waves, reps=1, candidates=c) for b, c in cands.items()}
+    sched, span = autotune.choose(counts, times, waves)
+    assert span > 0 and set(sched) == set(counts)
+    batches, ref = _mixed_inputs(mx, counts, k=13)
+    for b, bits in zip(batches, counts):
+        b.update(autotune.batch_args(sched[bits]))
+    plan = mx.MixedPlan(batches)
+    assert plan.njobs == sum(-(-n // sched[bits]["tile_instances"]) for bits, n in counts.items())
+    plan.launch(graph=True)
+    torch.cuda.synchronize()
+    for b, bits in zip(batches, counts):
+        s = sched[bits]
+        fam = s["flags"] & (mx.MX_IMPL_BLOCK | mx.MX_MUL_KARATSUBA)
+        alone = dev_ints(mx.modexp(b["ctx"], b["base"], b["exp"], bits, window=s["window"],
+                                   block="karatsuba" if fam == mx.MX_MUL_KARATSUBA else bool(fam)))
+        got = dev_ints(b["out"])
+        assert got == alone, (bits, s)
+        want = oracle_pool.results(("plan", bits), lambda: _plan_jobs(bits))
+        assert [got[i] for i in _plan_idx(bits)] == want, bits
+    plan.close()
+    for b in batches:
+        b["ctx"].close()
+
+
+def test_mixed_plan_lane_flags(mx):
+    """MX_ONE_LANE / MX_TWO_LANES pick the tile of a block batch (64 or 32 instances); two lanes exist for
+    the 3072- and 4096-bit schoolbook tiles only."""
+    import torch
+    counts = {3072: 65, 4096: 71}
+    batches, _ = _mixed_inputs(mx, counts, k=13)
+    for flags, tiles in ((mx.MX_ONE_LANE, 2 + 2), (mx.MX_TWO_LANES, 3 + 3)):
+        for b in batches:
+            b["flags"] = flags
+        plan = mx.MixedPlan(batches)
+        assert plan.njobs == tiles
+        plan.close()
+    ctx = mx.Context(wl.random_moduli(wl.stream(15, "moduli"), 2048, 4), 2048)
+    t = torch.zeros((4, ctx.words), dtype=torch.int64, device="cuda")
+    with pytest.raises(mx.MontError) as ei:
+        mx.MixedPlan([{"ctx": ctx, "base": t, "exp": t, "exp_bits": 2048, "out": t, "flags": mx.MX_TWO_LANES}])
+    assert ei.value.status == mx.MX_EUNSUPPORTED
+    ctx.close()
+    for b in batches:
+        b["ctx"].close()
 
 
 @pytest.mark.parametrize("bits", [2048, 4096])
