@@ -94,13 +94,15 @@ enum {
                           otherwise run four); a middle ground between latency
                           and throughput for a moderately loaded device; with
                           MX_ONE_LANE, MX_EINVAL; same results               */
-  MX_REDC_KARATSUBA = 64 /* mont_mul_batch / mont_sqr_batch only: the truncated
-                          high half of q N formed by one-level Karatsuba
-                          (Section 5, Karatsuba paragraph) from limb-wise half
-                          sums, so that every column is the schoolbook's;
-                          same results.  Register-resident classes (<= 2048
-                          bits), else MX_EUNSUPPORTED; with another MX_REDC_
-                          flag, MX_EINVAL; exponentiation: MX_EUNSUPPORTED   */
+  MX_MUL_KARATSUBA2 = 128, /* mp_mul_batch only: Karatsuba at two levels         */
+  MX_REDC_KARATSUBA = 64 /* the truncated high half of q N formed by one-level
+                          Karatsuba (Section 5, Karatsuba paragraph) from
+                          limb-wise half sums, so that every column is the
+                          schoolbook's; same results.  Single operations and
+                          exponentiation of the register-resident classes
+                          (<= 2048 bits), else MX_EUNSUPPORTED; with another
+                          MX_REDC_ flag, MX_EINVAL; not in the mixed launch
+                          or rsa_crt_batch                                   */
 };
 
 /* Montgomery contexts for `count` moduli of size class `bits` (Section 4:
@@ -198,6 +200,26 @@ mx_status modexp_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t window, uint
 /* The same for mont_mul_batch / mont_sqr_batch (0 for the register-resident
  * kernels, which need no workspace). */
 mx_status mont_ws_bytes(const mont_ctx *ctx, uint32_t n, uint32_t flags, size_t *bytes);
+
+/* ---- raw products --------------------------------------------------------------
+ * out[i] = a[i] * b[i], or a[i]^2 when b is NULL: the full product of two
+ * values of `bits` bits (1 <= bits <= 4256), without reduction -- the batch
+ * multiplication the paper measures on its own (Section 2, Algorithms 1 and 2;
+ * Section 3, Karatsuba; Table 6 goes to 4108 bits by schoolbook and 4154 by
+ * Karatsuba).  flags: 0 schoolbook (block product scanning), MX_MUL_KARATSUBA
+ * one level of Karatsuba above it, MX_MUL_KARATSUBA2 two levels; every method
+ * gives the same integers.  a, b: ceil(bits / 64) words per instance, only
+ * their low `bits` bits are used; out: ceil(2 bits / 64) words per instance.
+ * Operands are held as 148 limbs of 28 bits up to 4144 bits, else 152 (four
+ * blocks of 37 or 38 limbs; Karatsuba splits at block boundaries).  ws: a
+ * caller-owned device workspace of ws_bytes; n is done in as many launches as
+ * it holds (mp_mul_ws_bytes gives one launch's size; MX_EINVAL if it holds
+ * fewer than 64 instances).  Allocates nothing.  out must not alias a or b. */
+mx_status mp_mul_batch(const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t bits, uint32_t n,
+                       uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes of one mp_mul_batch launch over n instances. */
+mx_status mp_mul_ws_bytes(uint32_t bits, uint32_t n, uint32_t flags, size_t *bytes);
 
 /* ---- RSA private-key operations by the Chinese remainder theorem -----------
  * The application the paper's batched exponentiation is built for (Section

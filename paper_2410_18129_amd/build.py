@@ -41,14 +41,19 @@ def build(jobs=None, only=None, verbose=True):
                                           "-o", os.path.join(BUILD, "mx_abi.o")])]
     units.append(("mx_mixed", [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, "mx_mixed.hip"),
                                                 "-o", os.path.join(BUILD, "mx_mixed.o")]))
+    units.append(("mx_mul", [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, "mx_mul.hip"),
+                                              "-o", os.path.join(BUILD, "mx_mul.o")]))
     for b in classes:
         units.append(("class_%d" % b, [HIPCC] + FLAGS + ["-DMX_CLASS_BITS=%d" % b, "-c",
                                                        os.path.join(CSRC, "mx_class.hip"),
                                                        "-o", os.path.join(BUILD, "mx_class_%d.o" % b)]))
-        if b in CIOS_CLASSES:  # the word-interleaved kernels of the class, compiled alongside
+        if b in CIOS_CLASSES:  # the alternative-reduction kernels of the class, compiled alongside
             units.append(("cios_%d" % b, [HIPCC] + FLAGS + ["-DMX_CLASS_BITS=%d" % b, "-DMX_CIOS_UNIT", "-c",
                                                           os.path.join(CSRC, "mx_class.hip"),
                                                           "-o", os.path.join(BUILD, "mx_cios_%d.o" % b)]))
+            units.append(("kredc_%d" % b, [HIPCC] + FLAGS + ["-DMX_CLASS_BITS=%d" % b, "-DMX_KREDC_UNIT", "-c",
+                                                           os.path.join(CSRC, "mx_class.hip"),
+                                                           "-o", os.path.join(BUILD, "mx_kredc_%d.o" % b)]))
     for b in CRT_CLASSES:
         units.append(("crt_%d" % b, [HIPCC] + FLAGS + ["-DMX_CLASS_BITS=%d" % b, "-c", os.path.join(CSRC, "mx_crt.hip"),
                                                      "-o", os.path.join(BUILD, "mx_crt_%d.o" % b)]))
@@ -58,17 +63,18 @@ def build(jobs=None, only=None, verbose=True):
     jobs = jobs or min(len(units), max(1, os.cpu_count() or 1))
     t0 = time.time()
     # largest classes first so they overlap with the small ones
-    units.sort(key=lambda u: -int(u[0].split("_")[1]) if u[0].startswith(("class_", "cios_", "crt_")) else
-               (-4096 if u[0] == "mx_mixed" else 0))
+    units.sort(key=lambda u: -int(u[0].split("_")[1]) if u[0].startswith(("class_", "cios_", "kredc_", "crt_")) else
+               (-4096 if u[0] in ("mx_mixed", "mx_mul") else 0))
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = {ex.submit(_run, cmd): name for name, cmd in units}
         for f in cf.as_completed(futs):
             dt = f.result()
             if verbose:
                 print("  built %-10s %6.1fs" % (futs[f], dt), flush=True)
-    objs = ([os.path.join(BUILD, "mx_abi.o"), os.path.join(BUILD, "mx_mixed.o")] +
+    objs = ([os.path.join(BUILD, "mx_abi.o"), os.path.join(BUILD, "mx_mixed.o"), os.path.join(BUILD, "mx_mul.o")] +
             [os.path.join(BUILD, "mx_class_%d.o" % b) for b in CLASSES] +
             [os.path.join(BUILD, "mx_cios_%d.o" % b) for b in CLASSES if b in CIOS_CLASSES] +
+            [os.path.join(BUILD, "mx_kredc_%d.o" % b) for b in CLASSES if b in CIOS_CLASSES] +
             [os.path.join(BUILD, "mx_crt_%d.o" % b) for b in CRT_CLASSES])
     missing = [o for o in objs if not os.path.exists(o)]
     if missing:

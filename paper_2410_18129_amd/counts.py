@@ -1,7 +1,9 @@
 """Algorithmic work of the method: 28x28-bit partial products per operation.
 
 Host-side bookkeeping for throughput / roofline reporting.  n is the limb
-count of the size class, n = ceil((bits + 2) / 28).
+count of the size class, n = ceil((bits + 2) / 28): the work the method needs,
+not the padded count of the block kernels above 2048 bits (which compute
+whole 37-limb blocks and are charged only this).
 
   product  (Section 2): mul n^2, sqr n(n+1)/2 (off-diagonal once + diagonal)
   q        (Algorithm 6 step 1 / Algorithm 3 step 1): low half, n(n+1)/2
@@ -22,11 +24,12 @@ PEAK_MAD_PER_S = VALU_LANES * CLOCK_HZ  # 3.93e13 28x28->64 multiply-accumulates
 BLOCK_LIMBS = 37
 
 
-def limbs(bits):
-    """Limbs of a size class: ceil((bits + 2) / 28), rounded up to whole 37-limb
-    blocks above 2048 bits (block-level schoolbook)."""
+def limbs(bits, padded=False):
+    """Limbs of a size class: the method's ceil((bits + 2) / 28), which sets the algorithmic work
+    (110 at 3072 bits, 147 at 4096); padded=True gives the kernels' count, rounded up to whole 37-limb
+    blocks above 2048 bits (111 and 148), which also sets R."""
     n = (bits + 2 + LIMB_BITS - 1) // LIMB_BITS
-    if bits > 2048:
+    if padded and bits > 2048:
         n = BLOCK_LIMBS * ((n + BLOCK_LIMBS - 1) // BLOCK_LIMBS)
     return n
 
@@ -56,3 +59,11 @@ def table_scan_bytes(bits, ebits, w):
     n = limbs(bits)
     s = modexp_schedule(ebits, w)
     return s["windows"] * (1 << w) * n * 4
+
+
+def mul_products(bits, levels=0):
+    """Partial products of one raw product of bits-bit operands (n = ceil(bits / 28) limbs): n^2 by
+    schoolbook; with L levels of Karatsuba, 3^L products of ceil(n / 2^L)-limb parts."""
+    n = (bits + LIMB_BITS - 1) // LIMB_BITS
+    part = -(-n // (1 << levels))
+    return 3 ** levels * part * part

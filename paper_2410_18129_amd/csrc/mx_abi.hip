@@ -34,6 +34,10 @@ namespace mx {
 MX_DECL_CRT(1024)
 MX_DECL_CRT(2048)
 #undef MX_DECL_CRT
+// batched raw products (mx_mul.hip)
+uint32_t mul_raw_rows(uint32_t bits, int levels);
+hipError_t mul_raw(int levels, const uint64_t* a, const uint64_t* b, uint64_t* out, uint32_t bits, uint32_t win,
+                   uint32_t wout, uint32_t count, uint32_t* ws, uint32_t ws_bytes, hipStream_t st);
 }  // namespace mx
 
 namespace {
@@ -399,8 +403,6 @@ static mx_status modexp_args(const char* name, const mont_ctx* ctx, const uint32
   if (*impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
   *redc = redc_of(flags);
   if (mx_status rs = check_redc(name, ctx, *impl, *redc); rs != MX_OK) return rs;
-  if (*redc == mx::kRedcKara)
-    return fail(MX_EUNSUPPORTED, "%s: MX_REDC_KARATSUBA is built for mont_mul_batch / mont_sqr_batch only", name);
   if (window > 8) return fail(MX_EINVAL, "%s: window %u outside 1..8", name, window);
   if (!ctx_idx && n > ctx->count) return fail(MX_EINVAL, "%s: n=%u exceeds context count %u", name, n, ctx->count);
   *w = window ? window : default_window(ctx->bits);
@@ -621,6 +623,49 @@ mx_status modexp_ws_bytes(const mont_ctx* ctx, uint32_t n, uint32_t window, uint
   const uint32_t rows = ctx->ops->ws_rows(impl, true, w);
   const uint32_t chunk = fit_instances(rows, n ? n : 1, mx::kMaxWsBytes);
   *bytes = launch_bytes(rows, chunk ? chunk : 64);
+  return MX_OK;
+}
+
+// Karatsuba levels of a raw product's flags (0, 1, 2), or -1 for flags that are not a method.
+static int mul_levels(uint32_t flags) {
+  if (flags == 0) return 0;
+  if (flags == (uint32_t)MX_MUL_KARATSUBA) return 1;
+  if (flags == (uint32_t)MX_MUL_KARATSUBA2) return 2;
+  return -1;
+}
+
+mx_status mp_mul_ws_bytes(uint32_t bits, uint32_t n, uint32_t flags, size_t* bytes) {
+  if (!bytes) return fail(MX_EINVAL, "mp_mul_ws_bytes: bytes is NULL");
+  const int lv = mul_levels(flags);
+  if (lv < 0) return fail(MX_EINVAL, "mp_mul_ws_bytes: flags 0x%x are not a product method", flags);
+  const uint32_t rows = bits ? mx::mul_raw_rows(bits, lv) : 0u;
+  if (rows == 0) return fail(MX_EUNSUPPORTED, "mp_mul_ws_bytes: %u-bit operands (1 .. 4256 are built)", bits);
+  const uint32_t chunk = fit_instances(rows, n ? n : 1, mx::kMaxWsBytes);
+  *bytes = launch_bytes(rows, chunk ? chunk : 64);
+  return MX_OK;
+}
+
+mx_status mp_mul_batch(const uint64_t* a, const uint64_t* b, uint64_t* out, uint32_t bits, uint32_t n, uint32_t flags,
+                       void* ws, size_t ws_bytes, void* stream) {
+  const char* name = "mp_mul_batch";
+  const int lv = mul_levels(flags);
+  if (lv < 0) return fail(MX_EINVAL, "%s: flags 0x%x are not a product method", name, flags);
+  const uint32_t rows = bits ? mx::mul_raw_rows(bits, lv) : 0u;
+  if (rows == 0) return fail(MX_EUNSUPPORTED, "%s: %u-bit operands (1 .. 4256 are built)", name, bits);
+  if (n == 0) return MX_OK;
+  if (!a || !out || !ws) return fail(MX_EINVAL, "%s: NULL pointer", name);
+  const uint32_t chunk = fit_instances(rows, n, ws_bytes);
+  if (chunk == 0)
+    return fail(MX_EINVAL, "%s: a workspace of %zu bytes holds no 64-instance tile (%zu bytes)", name, ws_bytes,
+                launch_bytes(rows, 64));
+  const uint32_t win = words_for(bits), wout = words_for(2 * bits);
+  for (uint32_t off = 0; off < n; off += chunk) {
+    const uint32_t cnt = n - off < chunk ? n - off : chunk;
+    hipError_t e = mx::mul_raw(lv, a + (size_t)off * win, b ? b + (size_t)off * win : nullptr, out + (size_t)off * wout,
+                               bits, win, wout, cnt, (uint32_t*)ws, (uint32_t)launch_bytes(rows, cnt),
+                               (hipStream_t)stream);
+    if (e != hipSuccess) return launch_fail(e, name);
+  }
   return MX_OK;
 }
 

@@ -18,6 +18,7 @@ MX_OK, MX_EINVAL, MX_ENOMEM, MX_EDEVICE, MX_EUNSUPPORTED = 0, 1, 2, 3, 4
 MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA, MX_ONE_LANE, MX_REDC_CIOS, MX_TWO_LANES = \
     0, 1, 2, 4, 8, 16, 32
 MX_REDC_KARATSUBA = 64
+MX_MUL_KARATSUBA2 = 128
 SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
@@ -42,6 +43,8 @@ _SIGS = {
     "rsa_crt_batch_ws": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _U32, _P, _U32, _U32, _P, ctypes.c_size_t,
                                         _P]),
     "rsa_crt_ws_bytes": (ctypes.c_int, [_P, _U32, _U32, _U32, ctypes.POINTER(ctypes.c_size_t)]),
+    "mp_mul_batch": (ctypes.c_int, [_P, _P, _P, _U32, _U32, _U32, _P, ctypes.c_size_t, _P]),
+    "mp_mul_ws_bytes": (ctypes.c_int, [_U32, _U32, _U32, ctypes.POINTER(ctypes.c_size_t)]),
     "mx_mixed_plan_create": (ctypes.c_int, [ctypes.POINTER(_P), _P, _U32]),
     "mx_mixed_plan_launch": (ctypes.c_int, [_P, _P]),
     "mx_mixed_plan_launch_graph": (ctypes.c_int, [_P, _P]),
@@ -255,12 +258,13 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=Fal
 
 
 def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None, block=False,
-           one_lane=False, cios=False, two_lanes=False):
+           one_lane=False, cios=False, two_lanes=False, kara_redc=False):
     """base^exp mod N per instance; base: int64 [n, words], exp: int64 [n, ceil(exp_bits/64)].
 
     one_lane: block kernels keep one lane per instance for small batches too (MX_ONE_LANE);
     two_lanes: at most two lanes per instance (MX_TWO_LANES).
-    cios: word-interleaved Montgomery products (Algorithm 4, MX_REDC_CIOS; classes up to 2048 bits)."""
+    cios: word-interleaved Montgomery products (Algorithm 4, MX_REDC_CIOS; classes up to 2048 bits).
+    kara_redc: truncated high half of q N by one-level Karatsuba (MX_REDC_KARATSUBA; up to 2048 bits)."""
     n = base.shape[0]
     if out is None:
         import torch
@@ -271,7 +275,7 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
         _check_rows("exp", exp, n, words_for(exp_bits))
     _check_idx(ctx_idx, n, ctx)
     flags = (_redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0) |
-             (MX_TWO_LANES if two_lanes else 0))
+             (MX_TWO_LANES if two_lanes else 0) | (MX_REDC_KARATSUBA if kara_redc else 0))
     if n:  # one launch's workspace (0, a no-op, for arguments the call itself rejects)
         ctx.reserve(modexp_ws_bytes(ctx, n, window, flags=flags))
     _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,
@@ -283,7 +287,8 @@ class MixedPlan:
     """One persistent launch over several size-class batches (mx_mixed_plan_*).
 
     batches: list of dicts with keys ctx, base, exp, exp_bits, out and
-    optionally window, block (bool), ctx_idx, tile_cost.  The device buffers
+    optionally window, block (bool), karatsuba (bool), flags (MX_IMPL_BLOCK,
+    MX_MUL_KARATSUBA, MX_ONE_LANE, MX_TWO_LANES), ctx_idx, tile_cost.  The device buffers
     are captured by the plan; every launch reads and writes them.
     """
 
@@ -302,7 +307,8 @@ class MixedPlan:
             d.ctx, d.ctx_idx = ctx.handle, _ptr(b.get("ctx_idx"))
             d.base, d.exp, d.out = _ptr(base), _ptr(exp) if b["exp_bits"] else None, _ptr(out)
             d.n, d.exp_bits, d.window = n, b["exp_bits"], b.get("window", 0)
-            d.flags = (MX_MUL_KARATSUBA if b.get("karatsuba") else 0) | (MX_IMPL_BLOCK if b.get("block") else 0)
+            d.flags = ((MX_MUL_KARATSUBA if b.get("karatsuba") else 0) | (MX_IMPL_BLOCK if b.get("block") else 0) |
+                       int(b.get("flags", 0)))
             d.tile_cost = float(b.get("tile_cost", 0.0))
             self._keep.append(b)
         self._h = ctypes.c_void_p()
@@ -416,6 +422,37 @@ def rsa_crt_ws_bytes(ctx_p, n, window=0, plain=False, cios=False):
     nb = ctypes.c_size_t()
     _check(lib().rsa_crt_ws_bytes(ctx_p.handle, n, window, _redc_flags(plain, cios), ctypes.byref(nb)))
     return nb.value
+
+
+MUL_METHODS = {"schoolbook": 0, "karatsuba": MX_MUL_KARATSUBA, "karatsuba2": MX_MUL_KARATSUBA2}
+
+
+def mp_mul_ws_bytes(bits, n, method="schoolbook"):
+    nb = ctypes.c_size_t()
+    _check(lib().mp_mul_ws_bytes(bits, n, MUL_METHODS[method], ctypes.byref(nb)))
+    return nb.value
+
+
+def mp_mul(a, b, bits, method="schoolbook", out=None, ws=None, stream=None):
+    """Full products a[i] * b[i] (a[i]^2 when b is None) of bits-bit values (mp_mul_batch).
+
+    a, b: int64 device tensors [n, ceil(bits/64)]; out: [n, ceil(2 bits/64)]; ws: a device workspace
+    tensor (allocated here for one launch when None); method: schoolbook, karatsuba or karatsuba2."""
+    import torch
+    n = a.shape[0]
+    _check_rows("a", a, n, words_for(bits))
+    if b is not None:
+        _check_rows("b", b, n, words_for(bits))
+    if out is None:
+        out = torch.empty((n, words_for(2 * bits)), dtype=torch.int64, device=a.device)
+    _check_rows("out", out, n, words_for(2 * bits))
+    if ws is None:
+        ws = torch.empty(max(1, mp_mul_ws_bytes(bits, n, method)), dtype=torch.uint8, device=a.device)
+    if not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("ws: expected a contiguous device tensor")
+    _check(lib().mp_mul_batch(_ptr(a), _ptr(b), _ptr(out), bits, n, MUL_METHODS[method], _ptr(ws),
+                              ws.numel() * ws.element_size(), _stream_ptr(stream)))
+    return out
 
 
 def to_device(words_u64, device="cuda"):

@@ -51,19 +51,26 @@ def test_host_side_argument_errors_without_gpu():
     assert L.mont_mul_batch(None, None, None, None, None, 1, 0, None) == mx.MX_EINVAL
     assert L.modexp_batch(None, None, None, None, 8, 5, None, 1, 0, None) == mx.MX_EINVAL
     assert L.rsa_crt_batch(None, None, None, None, None, None, None, 0, None, 1, 0, None) == mx.MX_EINVAL
+    # raw products: methods, sizes and the workspace are checked before any launch
+    nb = ctypes.c_size_t()
+    assert L.mp_mul_ws_bytes(4108, 64, 0, ctypes.byref(nb)) == mx.MX_OK and nb.value > 0
+    assert L.mp_mul_ws_bytes(4257, 64, 0, ctypes.byref(nb)) == mx.MX_EUNSUPPORTED
+    assert L.mp_mul_ws_bytes(4108, 64, 3, ctypes.byref(nb)) == mx.MX_EINVAL
+    assert L.mp_mul_batch(None, None, None, 4108, 1, 0, None, 0, None) == mx.MX_EINVAL
+    assert L.mp_mul_batch(None, None, None, 4108, 0, 0, None, 0, None) == mx.MX_OK  # n = 0
 
 
 def test_header_constants_match_the_binding():
     """Status codes and flags have the same values in include/montexp.h and the Python binding."""
     from paper_2410_18129_amd import montexp
     src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
-    vals = dict((k, int(v)) for k, v in re.findall(r"\b(MX_[A-Z_]+)\s*=\s*(\d+)", src))
+    vals = dict((k, int(v)) for k, v in re.findall(r"\b(MX_[A-Z0-9_]+)\s*=\s*(\d+)", src))
     for name in ("MX_OK", "MX_EINVAL", "MX_ENOMEM", "MX_EDEVICE", "MX_EUNSUPPORTED", "MX_REDC_TRUNC",
                  "MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS", "MX_TWO_LANES",
-                 "MX_REDC_KARATSUBA"):
+                 "MX_REDC_KARATSUBA", "MX_MUL_KARATSUBA2"):
         assert vals[name] == getattr(montexp, name), name
     flags = [vals[k] for k in ("MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS",
-                               "MX_TWO_LANES", "MX_REDC_KARATSUBA")]
+                               "MX_TWO_LANES", "MX_REDC_KARATSUBA", "MX_MUL_KARATSUBA2")]
     assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)
 
 
