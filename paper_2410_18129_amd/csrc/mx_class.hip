@@ -4,11 +4,12 @@
 // larger classes use the block-level schoolbook (mx_block.hpp).  The
 // alternative-reduction kernels of a register-resident class (the
 // word-interleaved multiplication of Algorithm 4, and the Karatsuba-truncated
-// reduction) are built separately, with -DMX_CIOS_UNIT as well, so that they
-// compile in parallel with the rest of the class; that object exports the
-// launchers cios_mont_<bits>, cios_modexp_<bits> and kredc_mont_<bits>.
+// reduction) are built separately, with -DMX_CIOS_UNIT or -DMX_KREDC_UNIT as
+// well, so that they compile in parallel with the rest of the class; those
+// objects export the launchers cios_mont_<bits>, cios_modexp_<bits> and
+// kredc_mont_<bits> (MX_CIOS_UNIT), and kredc_modexp_<bits> (MX_KREDC_UNIT).
 #include "mx_block.hpp"
-#ifdef MX_CIOS_UNIT
+#if defined(MX_CIOS_UNIT) || defined(MX_KREDC_UNIT)
 #include "mx_kredc.hpp"
 #endif
 
@@ -32,6 +33,10 @@ hipError_t MX_CAT(cios_modexp_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t
 hipError_t MX_CAT(kredc_mont_, MX_CLASS_BITS)(bool sqr, const CtxDev& ctx, const uint32_t* cidx, const uint64_t* a,
                                               const uint64_t* b, uint64_t* out, uint32_t count, uint32_t coff,
                                               hipStream_t st);
+hipError_t MX_CAT(kredc_modexp_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
+                                                const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w,
+                                                uint64_t* out, uint32_t count, uint32_t* ws, uint32_t ws_bytes,
+                                                uint32_t coff, hipStream_t st);
 #endif
 
 #ifdef MX_CIOS_UNIT
@@ -61,6 +66,18 @@ hipError_t MX_CAT(cios_modexp_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t
                                                uint64_t* out, uint32_t count, uint32_t* ws, uint32_t ws_bytes,
                                                uint32_t coff, hipStream_t st) {
   hipLaunchKernelGGL((k_modexp_cios<kCiosN, words_for(MX_CLASS_BITS)>), dim3((count + 63) / 64), dim3(64), 0, st,
+                     ctx, cidx, base, ex, ebits, ewords, w, out, count, ws, ws_bytes, coff);
+  return hipGetLastError();
+}
+}  // namespace mx
+#elif defined(MX_KREDC_UNIT)
+static_assert(MX_CLASS_BITS <= 2048, "the Karatsuba-truncated kernels exist for the register-resident classes");
+constexpr int kKredcN = limbs_for(MX_CLASS_BITS);
+hipError_t MX_CAT(kredc_modexp_, MX_CLASS_BITS)(const CtxDev& ctx, const uint32_t* cidx, const uint64_t* base,
+                                                const uint64_t* ex, uint32_t ebits, uint32_t ewords, uint32_t w,
+                                                uint64_t* out, uint32_t count, uint32_t* ws, uint32_t ws_bytes,
+                                                uint32_t coff, hipStream_t st) {
+  hipLaunchKernelGGL((k_modexp_kredc<kKredcN, words_for(MX_CLASS_BITS)>), dim3((count + 63) / 64), dim3(64), 0, st,
                      ctx, cidx, base, ex, ebits, ewords, w, out, count, ws, ws_bytes, coff);
   return hipGetLastError();
 }
@@ -259,6 +276,9 @@ hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx
     if (redc == kRedcCios)
       return MX_CAT(cios_modexp_, MX_CLASS_BITS)(ctx, cidx, base, ex, ebits, ewords, w, out, count, ws, ws_bytes, coff,
                                                  st);
+    if (redc == kRedcKara)
+      return MX_CAT(kredc_modexp_, MX_CLASS_BITS)(ctx, cidx, base, ex, ebits, ewords, w, out, count, ws, ws_bytes,
+                                                  coff, st);
 #endif
     if constexpr (kTwoWaves) {
       if (trunc)
@@ -305,4 +325,4 @@ const ClassOps kOps = {kBits, kN, kHasBlk || kBlock, kHasKara, !kBlock, ctx_fn, 
 const ClassOps* MX_CAT(class_ops_, MX_CLASS_BITS)() { return &kOps; }
 
 }  // namespace mx
-#endif  // MX_CIOS_UNIT
+#endif  // MX_CIOS_UNIT / MX_KREDC_UNIT

@@ -224,7 +224,9 @@ __device__ __forceinline__ void stagger(uint32_t block, uint32_t w) {
 // CIOS: every Montgomery product is the word-interleaved one of Algorithm 4
 // (cios_mul); s_ctx then holds the modulus (rows 0 .. N-1) and a copy of Y,
 // the first operand of every product (rows N .. 2N-1), and TRUNC is unused.
-template <int N, int BW, bool TRUNC, bool CIOS = false>
+// KREDC: the truncated high half of every product's q N is formed by one-level
+// Karatsuba (kara_high_half) instead of redc_blk's schoolbook columns.
+template <int N, int BW, bool TRUNC, bool CIOS = false, bool KREDC = false>
 __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
                                             const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                             uint32_t ebits, uint32_t ewords, uint32_t w,
@@ -359,7 +361,13 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
         sqr_sb<N>(y, t);
       else
         mul_sb<N>(y, bsrc, t);
-      redc_blk<N, TRUNC>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, y);
+      if constexpr (KREDC) {  // truncated high half of q N by one-level Karatsuba (same value)
+        uint32_t q[N];
+        low_half_q<N, PlainMad>(t, [&](int i) { return sm[(N + i) * 64]; }, q);
+        kara_high_half<N, PlainMad>(t, q, [&](int j) { return sm[j * 64]; }, y);
+      } else {
+        redc_blk<N, TRUNC>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, y);
+      }
     }
     if (store_e >= 0) {
       const uint32_t s0 = (uint32_t)store_e * ent_bytes;

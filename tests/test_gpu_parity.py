@@ -34,20 +34,16 @@ def _moduli(bits, count, k=1):
 
 def _redcs(bits):
     """Reductions built for a class: truncated (Algorithm 6), plain (Algorithm 3) and, up to 2048 bits,
-    the word-interleaved CIOS (Algorithm 4); as keyword arguments of the binding."""
+    the word-interleaved CIOS (Algorithm 4) and the truncated high half of q*N formed by one-level
+    Karatsuba (Section 5); as keyword arguments of the binding."""
     r = {"trunc": {}, "plain": {"plain": True}}
     if bits <= 2048:
         r["cios"] = {"cios": True}
-    return r
-
-
-def _mont_redcs(bits):
-    """As _redcs, plus (single operations only, up to 2048 bits) the truncated high half of q*N formed by
-    one-level Karatsuba (Section 5)."""
-    r = _redcs(bits)
-    if bits <= 2048:
         r["kara"] = {"kara_redc": True}
     return r
+
+
+_mont_redcs = _redcs
 
 
 @pytest.mark.parametrize("bits", CLASSES)
@@ -287,12 +283,12 @@ def test_errors_and_noops(mx):
     with pytest.raises(mx.MontError) as ei:  # one reduction at a time
         mx.mont_sqr(ctx, a[:1], cios=True, kara_redc=True)
     assert ei.value.status == mx.MX_EINVAL
-    # the Karatsuba-truncated reduction has no exponentiation kernel
+    # the Karatsuba-truncated reduction excludes the other reductions
     import ctypes
     ob = torch.zeros((1, 1), dtype=torch.int64, device="cuda")
     assert mx.lib().modexp_batch(ctx.handle, None, ctypes.c_void_p(one.data_ptr()), ctypes.c_void_p(one.data_ptr()),
-                                 8, 0, ctypes.c_void_p(ob.data_ptr()), 1, mx.MX_REDC_KARATSUBA,
-                                 None) == mx.MX_EUNSUPPORTED
+                                 8, 0, ctypes.c_void_p(ob.data_ptr()), 1, mx.MX_REDC_KARATSUBA | mx.MX_REDC_CIOS,
+                                 None) == mx.MX_EINVAL
     ctx.close()
     # CIOS exists for the register-resident kernels only: not for the block kernels or above 2048 bits
     for bits, block in ((2048, True), (3072, False)):
