@@ -8,7 +8,7 @@ HBM.  The JSON line also carries the other workloads (8 x 1024-bit; 16384 x
 4096-bit schoolbook vs Karatsuba; the 200k mixed-size persistent launch; the
 serving loop's p50/p99) and the oracle timed on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu] [--serve-full]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu]
 """
 import argparse
 import hashlib
@@ -36,8 +36,9 @@ def parse():
     ap.add_argument("--window", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline only (no other workloads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg")
-    ap.add_argument("--serve-full", action="store_true", help="serving sweep 50k..400k req/s, 200k requests each")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle instances (0 = 2 per core)")
+    ap.add_argument("--only", choices=("headline", "c3"), default=None,
+                    help="one launch configuration alone, for profiling: the headline exponentiation (window "
+                         "--window) or the 16384 x 4096-bit block exponentiation at window 6")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device-to-device three times (calibrates FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -81,31 +82,69 @@ def measured_traffic(kernel_id):
     return float(t.group(1))
 
 
-def cpu_baseline(bits, sample, cores):
-    """The oracle (plain C schoolbook + bit-serial reduction + square-and-multiply)
-    on a bounded sample of the same workload, one process per core."""
+def _oracle_jobs_rate(jobs, cores, min_s):
+    """Rate of the oracle on `jobs` [(base, exp, N, ebits)], one process per core, repeating the whole
+    sample until min_s seconds of wall time have passed; (instances per second, repeats, wall seconds)."""
     import multiprocessing as mp
-    from paper_2410_18129_amd import workload as wl
-    mods = wl.random_moduli(wl.stream(2, "moduli"), bits, sample)
-    base = wl.random_below_fast(wl.stream(2, "bases"), mods, bits)
-    exps = wl.random_exponents(wl.stream(2, "exps"), bits, sample)
-    M, B, E = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
-    chunks = [(B[i::cores], E[i::cores], M[i::cores], bits) for i in range(cores)]
-    t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(cores) as pool:
-        pool.map(_oracle_chunk, chunks)
-    dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "modexp/s", "cores": cores, "kind": "oracle",
-            "sample": "%d x %d-bit modexp (%d-bit exponents), %d worker processes, %.1f s wall" %
-                      (sample, bits, bits, cores, dt)}
+    chunks = [jobs[i::cores] for i in range(cores)]
+    chunks = [c for c in chunks if c]
+    reps, t0 = 0, time.perf_counter()
+    with mp.get_context("fork").Pool(len(chunks)) as pool:
+        while True:
+            pool.map(_oracle_chunk, chunks)
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_s:
+                break
+    return len(jobs) * reps / dt, reps, dt
 
 
-def _oracle_chunk(args):
+def _oracle_chunk(jobs):
     import oracle
-    b, e, m, bits = args
-    if b:
-        oracle.modexp_many(b, e, m, bits)
-    return len(b)
+    for b, e, m, ebits in jobs:
+        oracle.modexp(b, e, m, ebits)
+    return len(jobs)
+
+
+def _sample_jobs(bits, n_total, k, idx):
+    """(base, exp, N, ebits) of the instances idx of workload k's seeded n_total-instance batch."""
+    from paper_2410_18129_amd import workload as wl
+    mods = wl.random_moduli(wl.stream(k, "moduli"), bits, n_total)
+    base = wl.random_below_fast(wl.stream(k, "bases"), mods, bits)
+    exps = wl.random_exponents(wl.stream(k, "exps"), bits, n_total)
+    M, B, E = wl.words_to_ints(mods[idx]), wl.words_to_ints(base[idx]), wl.words_to_ints(exps[idx])
+    return [(b, e, m, bits) for b, e, m in zip(B, E, M)]
+
+
+def cpu_baseline(cores, min_s=10.0):
+    """The oracle (plain C schoolbook + bit-serial reduction + square-and-multiply) on bounded samples
+    of the workloads, one process per core, each leg at least min_s seconds of wall time: all 8
+    instances of the 1024-bit workload (repeated), 512 of the 65536 x 2048-bit headline (the value),
+    64 of the 16384 x 4096-bit workload and 1000 of the 200k mixed workload stratified by class
+    (400 / 350 / 150 / 100)."""
+    import numpy as np
+    from paper_2410_18129_amd import workload as wl
+    legs = {}
+    spread = lambda n, m: np.arange(m) * (n // m)
+    r, reps, dt = _oracle_jobs_rate(_sample_jobs(2048, 65536, 2, spread(65536, 512)), cores, min_s)
+    main = {"value": r, "unit": "modexp/s", "cores": cores, "kind": "oracle",
+            "sample": "512 of the 65536 seeded 2048-bit instances (2048-bit exponents, every 128th), %d worker "
+                      "processes, %d pass(es), %.1f s wall" % (cores, reps, dt)}
+    r1, reps1, dt1 = _oracle_jobs_rate(_sample_jobs(1024, 8, 1, np.arange(8)), cores, min_s)
+    legs["c1_1024x8"] = {"modexp_per_s": r1, "sample": "all 8 instances, %d passes, %.1f s wall" % (reps1, dt1)}
+    r3, reps3, dt3 = _oracle_jobs_rate(_sample_jobs(4096, 16384, 3, spread(16384, 64)), cores, min_s)
+    legs["c3_4096x16384"] = {"modexp_per_s": r3, "sample": "64 instances, every 256th, %d pass(es), %.1f s wall"
+                                                           % (reps3, dt3)}
+    sizes = wl.size_mix(wl.stream(4, "sizes"), 200000)
+    jobs = []
+    for c, m in ((1024, 400), (2048, 350), (3072, 150), (4096, 100)):
+        n_c = int((sizes == c).sum())
+        jobs += _sample_jobs(c, n_c, 4 + c, spread(n_c, m))
+    r4, reps4, dt4 = _oracle_jobs_rate(jobs, cores, min_s)
+    legs["c4_mixed_200k"] = {"modexp_per_s": r4, "sample": "1000 instances stratified 400/350/150/100 by class, "
+                                                           "%d pass(es), %.1f s wall" % (reps4, dt4)}
+    main["legs"] = legs
+    return main
 
 
 class Batch:
@@ -162,12 +201,16 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     bits, n, w = a.bits, a.batch, a.window
+    if a.only:
+        only_line(a, mx, counts, dev, stream)
+        return
 
     # ---- headline: config 2, 65536 x 2048-bit, window 5, truncated ---------
     b2 = Batch(mx, bits, n, 2, dev)
 
-    def step(plain=False, win=w, cios=False):
-        mx.modexp(b2.ctx, b2.base, b2.exp, bits, window=win, out=b2.out, plain=plain, cios=cios, stream=stream)
+    def step(plain=False, win=w, cios=False, kara_redc=False):
+        mx.modexp(b2.ctx, b2.base, b2.exp, bits, window=win, out=b2.out, plain=plain, cios=cios, kara_redc=kara_redc,
+                  stream=stream)
 
     wall, kms = time_launches(step, a.steps, a.warmup, stream)
     value = n * a.steps / wall
@@ -204,6 +247,11 @@ def main():
     res["cios"] = {"value": vc, "unit": "modexp/s", "kernel_ms": kc,
                    "frac": counts.modexp_products(bits, bits, w, cios=True) * n / (kc * 1e-3) / counts.PEAK_MAD_PER_S}
     res["trunc_vs_cios"] = value / vc
+    # the truncated high half of q*N by one-level Karatsuba (Section 5): the same products, more additions
+    wall_k, kms_k = time_launches(lambda: step(kara_redc=True), max(2, a.steps // 2), 1, stream)
+    vk = n * len(kms_k) / wall_k
+    res["kara_redc"] = {"value": vk, "unit": "modexp/s", "kernel_ms": sum(kms_k) / len(kms_k)}
+    res["trunc_vs_kara_redc"] = value / vk
     # the window the library picks for this class (3: the table stays in the last-level cache)
     tuned = {}
     for plain in (False, True):
@@ -249,8 +297,29 @@ def main():
     if not a.no_cpu:
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         cores = max(1, min(cores, 16))
-        res["cpu_baseline"] = cpu_baseline(bits, a.cpu_sample or 2 * cores, cores)
+        res["cpu_baseline"] = cpu_baseline(cores)
+        progress("oracle CPU baseline done")
     print(json.dumps(res), flush=True)
+
+
+def only_line(a, mx, counts, dev, stream):
+    """One configuration's launches alone (for a profiler run): prints its kernel time per launch."""
+    if a.only == "headline":
+        b = Batch(mx, a.bits, a.batch, 2, dev)
+        fn = lambda: mx.modexp(b.ctx, b.base, b.exp, a.bits, window=a.window, out=b.out, stream=stream)
+        work = counts.modexp_products(a.bits, a.bits, a.window) * b.n
+        name = "%d x %d-bit modexp, window %d" % (b.n, a.bits, a.window)
+    else:
+        b = Batch(mx, 4096, 16384, 3, dev)
+        fn = lambda: mx.modexp(b.ctx, b.base, b.exp, 4096, window=6, out=b.out, block=True, stream=stream)
+        work = counts.modexp_products(4096, 4096, 6) * b.n
+        name = "16384 x 4096-bit modexp, window 6, block schoolbook"
+    wall, kms = time_launches(fn, a.steps, a.warmup, stream)
+    kavg = sum(kms) / len(kms)
+    print(json.dumps({"only": name, "steps": a.steps, "warmup": a.warmup, "ms_per_step": wall * 1e3 / a.steps,
+                      "kernel_ms": kavg, "kernel_ms_each": kms,
+                      "frac": work / (kavg * 1e-3) / counts.PEAK_MAD_PER_S}), flush=True)
+    b.ctx.close()
 
 
 def rsa_crt_workload(mx, counts, dev, stream, nr=65536):
@@ -293,6 +362,7 @@ def rsa_crt_workload(mx, counts, dev, stream, nr=65536):
 def other_workloads(a, mx, counts, dev, stream):
     import torch
     from paper_2410_18129_amd import serving
+    from paper_2410_18129_amd import workload as wl
     out = {}
     # ---- config 1: 8 x 1024-bit ------------------------------------------------
     b1 = Batch(mx, 1024, 8, 1, dev)
@@ -323,39 +393,76 @@ def other_workloads(a, mx, counts, dev, stream):
                                              one_lane=True, stream=stream), 2, 1, stream)
     c3["modexp_per_s_schoolbook_one_lane"] = b3.n * 2 / wl_
     c3["schoolbook_vs_karatsuba_one_lane"] = c3["modexp_per_s_schoolbook_one_lane"] / c3["modexp_per_s_karatsuba"]
+    # raw products at Table 6's largest sizes (limb counts 147 and 149), schoolbook and Karatsuba at one
+    # and two levels, 16384 seeded instances each
+    g = wl.stream(3, "ops_a")
+    raw = {}
+    for pbits in (4108, 4154):
+        a_ = mx.to_device(wl.random_words(g, pbits, b3.n), dev)
+        b_ = mx.to_device(wl.random_words(g, pbits, b3.n), dev)
+        o_ = torch.empty((b3.n, mx.words_for(2 * pbits)), dtype=torch.int64, device=dev)
+        line = {}
+        for lv, m in enumerate(("schoolbook", "karatsuba", "karatsuba2")):
+            ws_ = torch.empty(mx.mp_mul_ws_bytes(pbits, b3.n, m), dtype=torch.uint8, device=dev)
+            wl_, k = time_launches(lambda: mx.mp_mul(a_, b_, pbits, method=m, out=o_, ws=ws_, stream=stream), 10, 2,
+                                   stream)
+            kms = sum(k) / len(k)
+            line[m] = {"products_per_s": b3.n * 10 / wl_, "kernel_ms": kms,
+                       "frac": counts.mul_products(pbits, lv) * b3.n / (kms * 1e-3) / counts.PEAK_MAD_PER_S,
+                       "partial_products": counts.mul_products(pbits, lv)}
+            del ws_
+        line["karatsuba_vs_schoolbook"] = line["karatsuba"]["products_per_s"] / line["schoolbook"]["products_per_s"]
+        line["karatsuba2_vs_schoolbook"] = (line["karatsuba2"]["products_per_s"] /
+                                            line["schoolbook"]["products_per_s"])
+        raw[str(pbits)] = line
+    c3["raw_products_16384"] = raw
     out["c3_4096x16384"] = c3
     progress("16384 x 4096-bit done")
     out["rsa2048_crt"] = rsa_crt_workload(mx, counts, dev, stream)
     progress("CRT-RSA done")
     b3.ctx.close()
     del b3
-    # ---- config 4: 200k mixed sizes, one persistent launch ------------------------------
-    from paper_2410_18129_amd import workload as wl
+    # ---- config 4: 200k mixed sizes, one persistent launch, schedule per class from the autotuner ----
+    from paper_2410_18129_amd import autotune
     sizes = wl.size_mix(wl.stream(4, "sizes"), 200000)
-    batches, nb = [], {}
-    for c in (1024, 2048, 3072, 4096):
-        nb[c] = int((sizes == c).sum())
-        bb = Batch(mx, c, nb[c], 4 + c, dev)
-        batches.append(bb)
-    plan = mx.MixedPlan([{"ctx": bb.ctx, "base": bb.base, "exp": bb.exp, "exp_bits": bb.bits, "out": bb.out,
-                          "window": 3 if bb.bits <= 2048 else 5} for bb in batches])
-    wl_, k = time_launches(lambda: plan.launch(stream=stream, graph=True), 2, 1, stream)
-    work = sum(counts.modexp_products(bb.bits, bb.bits, 3 if bb.bits <= 2048 else 5) * bb.n for bb in batches)
-    out["c4_mixed_200k"] = {"modexp_per_s": 200000 * 2 / wl_, "ms_per_launch": wl_ * 1e3 / 2,
-                            "counts": nb, "windows": plan.windows, "jobs": plan.njobs, "persistent_waves": plan.nslots,
-                            "frac": work / (sum(k) / len(k) * 1e-3) / counts.PEAK_MAD_PER_S, "hip_graph": True}
+    nb = {c: int((sizes == c).sum()) for c in (1024, 2048, 3072, 4096)}
+    t0 = time.perf_counter()
+    sched, model_ms = autotune.plan_for_mix(nb)
+    tune_s = time.perf_counter() - t0
+    progress("autotuner done (%.1f s)" % tune_s)
+    batches = [Batch(mx, c, nb[c], 4 + c, dev) for c in nb]
+
+    def mixed_line(args_of):
+        plan = mx.MixedPlan([dict({"ctx": bb.ctx, "base": bb.base, "exp": bb.exp, "exp_bits": bb.bits, "out": bb.out},
+                                  **args_of(bb.bits)) for bb in batches])
+        wl_, k = time_launches(lambda: plan.launch(stream=stream, graph=True), 2, 1, stream)
+        work = sum(counts.modexp_products(bb.bits, bb.bits, w) * bb.n for bb, w in zip(batches, plan.windows))
+        line = {"modexp_per_s": 200000 * 2 / wl_, "ms_per_launch": wl_ * 1e3 / 2, "windows": plan.windows,
+                "jobs": plan.njobs, "persistent_waves": plan.nslots,
+                "frac": work / (sum(k) / len(k) * 1e-3) / counts.PEAK_MAD_PER_S}
+        plan.close()
+        return line
+
+    c4 = mixed_line(lambda bits: autotune.batch_args(sched[bits]))
+    c4.update({"counts": nb, "hip_graph": True, "schedule": {str(b): sched[b] for b in sched},
+               "schedule_source": "autotuner: tile times of every candidate (window, kernel family, lanes per "
+                                  "instance) measured in the persistent kernel, choice by the modelled makespan",
+               "model_ms": model_ms, "tune_s": tune_s})
+    # the hand-set schedule of earlier measurements (windows 3 / 5, default lanes), for comparison
+    hand = mixed_line(lambda bits: {"window": 3 if bits <= 2048 else 5})
+    c4["handset_ms_per_launch"] = hand["ms_per_launch"]
+    out["c4_mixed_200k"] = c4
     progress("200k mixed launch done")
-    offline = 200000 * 2 / wl_
-    plan.close()
+    offline = c4["modexp_per_s"]
     for bb in batches:
         bb.ctx.close()
     del batches
     torch.cuda.synchronize()
     # ---- config 5: serving, Poisson arrivals over 2000 resident moduli ---------------------
-    rates = (50e3, 100e3, 200e3, 300e3, 400e3) if a.serve_full else (50e3, 100e3, 200e3, 400e3)
-    # a trace spans several batch durations of the slowest class (one 4096-bit exponentiation per
-    # lane takes over a second), so that throughput is not just the fill and drain of a burst
-    span_s, nmin = (5.0, 200000) if a.serve_full else (3.0, 100000)
+    rates = (50e3, 100e3, 200e3, 300e3, 400e3)
+    # at least 200k requests per rate, and a trace of at least 3 s (several batch durations of the
+    # slowest class), so that throughput is not just the fill and drain of a burst
+    span_s, nmin = 3.0, 200000
     # SERVE_SLOTS execution slots (a stream and a workspace each) per class, each stream on its own
     # hardware queue; batches of a class are paced about a batch duration / SERVE_SLOTS apart
     maxb = {1024: 65536, 2048: 65536, 3072: 32768, 4096: 32768}
