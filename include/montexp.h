@@ -38,9 +38,10 @@
  *    its tiles); launch or device errors give MX_EDEVICE; mont_last_error()
  *    returns a thread-local message for the last non-OK status.  No call
  *    aborts.
- *  - Device-data preconditions (a, b < 2N; base < N) are not checked: a
- *    violation gives an unspecified value, never an out-of-bounds access.
- *    ctx_idx entries >= the context count are replaced by 0.
+ *  - Device-data preconditions (a, b < 2N; base < N) are checked only on
+ *    request (MX_CHECK_INPUTS, a debugging aid); unchecked, a violation gives
+ *    an unspecified value, never an out-of-bounds access.  ctx_idx entries
+ *    >= the context count are replaced by 0.
  *  - Compared with the call list of the hot path: mont_ctx_query also
  *    returns the limb width, mont_ctx_export also returns R mod N, and the
  *    mixed-size launch is a plan (mx_mixed_plan_*) built once and launched
@@ -95,6 +96,13 @@ enum {
                           and throughput for a moderately loaded device; with
                           MX_ONE_LANE, MX_EINVAL; same results               */
   MX_MUL_KARATSUBA2 = 128, /* mp_mul_batch only: Karatsuba at two levels         */
+  MX_CHECK_INPUTS = 256, /* debugging: before the work, check the device-data
+                          preconditions (a, b < 2N for mont_mul_batch and
+                          mont_sqr_batch; base < N for the modexp_batch calls)
+                          with a small kernel; the call then waits for the
+                          stream, and gives MX_EINVAL naming the count and the
+                          first offending instance, launching nothing else.
+                          The check branches on the data: not for secrets   */
   MX_REDC_KARATSUBA = 64 /* the truncated high half of q N formed by one-level
                           Karatsuba (Section 5, Karatsuba paragraph) from
                           limb-wise half sums, so that every column is the

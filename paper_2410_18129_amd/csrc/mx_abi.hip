@@ -189,6 +189,57 @@ static mx_status check_redc(const char* name, const mont_ctx* ctx, int impl, int
   return MX_OK;
 }
 
+// ---- device-data preconditions, checked on request (MX_CHECK_INPUTS) ------------------------
+// flag[0] counts the instances whose value v is not below mult * N of their context, flag[1] is the
+// first of them.  A debugging aid: unlike the method's kernels, this check branches on the data.
+__global__ void k_check_clear(uint32_t* flag) {
+  if (threadIdx.x == 0) flag[0] = 0u;
+  if (threadIdx.x == 1) flag[1] = 0xFFFFFFFFu;
+}
+
+__global__ void k_check_below(mx::CtxDev ctx, const uint32_t* __restrict__ cidx, const uint64_t* __restrict__ v,
+                              uint32_t words, uint32_t limbs, uint32_t mult, uint32_t count, uint32_t coff,
+                              uint32_t* flag) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint32_t c = cidx ? cidx[i] : i + coff;
+  c = c < ctx.count ? c : 0u;
+  const uint64_t* x = v + (size_t)i * words;
+  // v - mult N over the limbs of N, low to high; a negative final carry means v < mult N
+  int64_t carry = 0;
+  for (uint32_t k = 0; k < limbs; ++k) {
+    const uint32_t bit = 28u * k, wd = bit >> 6, off = bit & 63u;
+    uint64_t t = wd < words ? x[wd] >> off : 0ull;
+    if (off > 36u && wd + 1 < words) t |= x[wd + 1] << (64u - off);
+    const int64_t d = (int64_t)(t & 0xFFFFFFFull) - (int64_t)mult * (int64_t)ctx.n[(size_t)k * ctx.stride + c] + carry;
+    carry = d >> 28;  // arithmetic shift: floor division
+  }
+  bool high = false;  // bits of v above the limbs
+  const uint32_t top = 28u * limbs;
+  for (uint32_t wd = top >> 6; wd < words; ++wd) high |= (wd == (top >> 6) ? x[wd] >> (top & 63u) : x[wd]) != 0ull;
+  if (carry >= 0 || high) {
+    atomicAdd(&flag[0], 1u);
+    atomicMin(&flag[1], i);
+  }
+}
+
+// Checks that the n values at v (words each) are below mult * N of their contexts, with 8 bytes of
+// device memory at `flag`; waits for the stream.  MX_EINVAL names the violations.
+static mx_status check_inputs(const char* name, const mont_ctx* ctx, const uint32_t* cidx, const uint64_t* v,
+                              uint32_t words, uint32_t mult, uint32_t n, void* flag, hipStream_t st, const char* what) {
+  uint32_t* f = (uint32_t*)flag;
+  hipLaunchKernelGGL(k_check_clear, dim3(1), dim3(64), 0, st, f);
+  hipLaunchKernelGGL(k_check_below, dim3((n + 255) / 256), dim3(256), 0, st, ctx->dev, cidx, v, words, ctx->limbs, mult,
+                     n, 0u, f);
+  hipError_t e = hipGetLastError();
+  uint32_t h[2] = {0u, 0u};
+  if (e == hipSuccess) e = hipMemcpyAsync(h, f, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return dev_fail(e, name);
+  if (h[0]) return fail(MX_EINVAL, "%s: %u of %u instances violate %s (first: instance %u)", name, h[0], n, what, h[1]);
+  return MX_OK;
+}
+
 // Library workspace a context reserves at init: one launch over its moduli at the default window,
 // up to this size.
 constexpr size_t kInitWsBytes = 256ull << 20;
@@ -341,7 +392,8 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n == 0) return MX_OK;
   if (!a || !out || (!sqr && !b)) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
-  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_REDC_CIOS | MX_REDC_KARATSUBA))
+  if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_REDC_CIOS | MX_REDC_KARATSUBA |
+                          MX_CHECK_INPUTS))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
   const int impl = impl_of(ctx, flags);
   if (impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
@@ -354,6 +406,14 @@ static mx_status mont_common(const char* name, const mont_ctx* ctx, const uint32
   const uint32_t mw = words_for(28 * ctx->limbs);
   const uint32_t rows = ctx->ops->ws_rows(impl, false, 0);
   hipStream_t st = (hipStream_t)stream;
+  if (flags & MX_CHECK_INPUTS) {  // a, b < 2N, with 8 bytes of the context's workspace; waits for the stream
+    WsTurn ct(mctx, st);
+    if (ct.err != hipSuccess) return dev_fail(ct.err, name);
+    mx_status cs = check_inputs(name, ctx, ctx_idx, a, mw, 2, n, mctx->ws, st, "a < 2N");
+    if (cs == MX_OK && !sqr) cs = check_inputs(name, ctx, ctx_idx, b, mw, 2, n, mctx->ws, st, "b < 2N");
+    (void)ct.done();
+    if (cs != MX_OK) return cs;
+  }
   if (rows == 0) {  // register-resident kernels: no workspace
     hipError_t e = ctx->ops->mont(impl, redc, sqr, ctx->dev, ctx_idx, a, b, out, n, nullptr, 0, 0,
                                   0u, st);
@@ -395,7 +455,7 @@ static mx_status modexp_args(const char* name, const mont_ctx* ctx, const uint32
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n && (!base || !out || (exp_bits && !exp))) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
   if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_REDC_CIOS |
-                          MX_TWO_LANES | MX_REDC_KARATSUBA))
+                          MX_TWO_LANES | MX_REDC_KARATSUBA | MX_CHECK_INPUTS))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
   if ((flags & MX_ONE_LANE) && (flags & MX_TWO_LANES))
     return fail(MX_EINVAL, "%s: MX_ONE_LANE and MX_TWO_LANES exclude each other", name);
@@ -446,6 +506,13 @@ mx_status modexp_batch(const mont_ctx* ctx, const uint32_t* ctx_idx, const uint6
   mont_ctx* c = const_cast<mont_ctx*>(ctx);
   WsTurn turn(c, (hipStream_t)stream);
   if (turn.err != hipSuccess) return dev_fail(turn.err, name);
+  if (flags & MX_CHECK_INPUTS) {  // base < N, with 8 bytes of the workspace; waits for the stream
+    rs = check_inputs(name, ctx, ctx_idx, base, words_for(ctx->bits), 1, n, c->ws, (hipStream_t)stream, "base < N");
+    if (rs != MX_OK) {
+      (void)turn.done();
+      return rs;
+    }
+  }
   rs = modexp_launches(name, ctx, impl, redc, ctx_idx, base, exp, exp_bits, w, out, n, c->ws, c->ws_bytes, false,
                        (hipStream_t)stream);
   const hipError_t e = turn.done();
@@ -464,6 +531,11 @@ mx_status modexp_batch_ws(const mont_ctx* ctx, const uint32_t* ctx_idx, const ui
   if (rs != MX_OK || n == 0) return rs;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
+  if (flags & MX_CHECK_INPUTS) {  // base < N, with 8 bytes of the caller's workspace; waits for the stream
+    if (ws_bytes < 8) return fail(MX_EINVAL, "%s: workspace of %zu bytes", name, ws_bytes);
+    rs = check_inputs(name, ctx, ctx_idx, base, words_for(ctx->bits), 1, n, ws, (hipStream_t)stream, "base < N");
+    if (rs != MX_OK) return rs;
+  }
   return modexp_launches(name, ctx, impl, redc, ctx_idx, base, exp, exp_bits, w, out, n, ws, ws_bytes, true,
                          (hipStream_t)stream);
 }
@@ -488,6 +560,10 @@ mx_status modexp_batch_noalloc(const mont_ctx* ctx, const uint32_t* ctx_idx, con
     return fail(MX_EDEVICE, "%s: no scratch address for device %d: %s", name, ctx->device, hipGetErrorString(serr));
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(MX_EDEVICE, "%s: cannot select device", name);
+  if (flags & MX_CHECK_INPUTS) {  // base < N, with 8 bytes of the scratch; waits for the stream
+    rs = check_inputs(name, ctx, ctx_idx, base, words_for(ctx->bits), 1, n, ptr, (hipStream_t)stream, "base < N");
+    if (rs != MX_OK) return rs;
+  }
   // one launch (need <= kScratchBytes < 2 GiB); every row a kernel reads it has written first in the
   // same launch, so nothing in the scratch has to start at zero
   return modexp_launches(name, ctx, impl, redc, ctx_idx, base, exp, exp_bits, w, out, n, ptr, kScratchBytes, true,

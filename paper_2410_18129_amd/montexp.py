@@ -19,6 +19,7 @@ MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA, MX_ONE_LANE, MX_R
     0, 1, 2, 4, 8, 16, 32
 MX_REDC_KARATSUBA = 64
 MX_MUL_KARATSUBA2 = 128
+MX_CHECK_INPUTS = 256
 SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
@@ -225,7 +226,7 @@ def _reserve_mont(ctx, n, flags):
 
 
 def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=False, cios=False,
-             kara_redc=False):
+             kara_redc=False, check_inputs=False):
     """REDC(a*b) per instance; a, b: int64 device tensors [n, mont_words]."""
     n = a.shape[0]
     if out is None:
@@ -234,7 +235,8 @@ def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=
     for nm, t in (("a", a), ("b", b), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_REDC_KARATSUBA if kara_redc else 0)
+    flags = (_redc_flags(plain, cios) | _impl_flags(block) | (MX_REDC_KARATSUBA if kara_redc else 0) |
+             (MX_CHECK_INPUTS if check_inputs else 0))
     _reserve_mont(ctx, n, flags)
     _check(lib().mont_mul_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(b), _ptr(out), n, flags,
                                 _stream_ptr(stream)))
@@ -242,7 +244,7 @@ def mont_mul(ctx, a, b, out=None, ctx_idx=None, plain=False, stream=None, block=
 
 
 def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=False, cios=False,
-             kara_redc=False):
+             kara_redc=False, check_inputs=False):
     """REDC(a^2) per instance; a: int64 device tensor [n, mont_words]."""
     n = a.shape[0]
     if out is None:
@@ -251,20 +253,22 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=Fal
     for nm, t in (("a", a), ("out", out)):
         _check_rows(nm, t, n, ctx.mont_words)
     _check_idx(ctx_idx, n, ctx)
-    flags = _redc_flags(plain, cios) | _impl_flags(block) | (MX_REDC_KARATSUBA if kara_redc else 0)
+    flags = (_redc_flags(plain, cios) | _impl_flags(block) | (MX_REDC_KARATSUBA if kara_redc else 0) |
+             (MX_CHECK_INPUTS if check_inputs else 0))
     _reserve_mont(ctx, n, flags)
     _check(lib().mont_sqr_batch(ctx.handle, _ptr(ctx_idx), _ptr(a), _ptr(out), n, flags, _stream_ptr(stream)))
     return out
 
 
 def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None, block=False,
-           one_lane=False, cios=False, two_lanes=False, kara_redc=False):
+           one_lane=False, cios=False, two_lanes=False, kara_redc=False, check_inputs=False):
     """base^exp mod N per instance; base: int64 [n, words], exp: int64 [n, ceil(exp_bits/64)].
 
     one_lane: block kernels keep one lane per instance for small batches too (MX_ONE_LANE);
     two_lanes: at most two lanes per instance (MX_TWO_LANES).
     cios: word-interleaved Montgomery products (Algorithm 4, MX_REDC_CIOS; classes up to 2048 bits).
-    kara_redc: truncated high half of q N by one-level Karatsuba (MX_REDC_KARATSUBA; up to 2048 bits)."""
+    kara_redc: truncated high half of q N by one-level Karatsuba (MX_REDC_KARATSUBA; up to 2048 bits).
+    check_inputs: check base < N first (MX_CHECK_INPUTS; the call then waits for the stream)."""
     n = base.shape[0]
     if out is None:
         import torch
@@ -275,7 +279,8 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
         _check_rows("exp", exp, n, words_for(exp_bits))
     _check_idx(ctx_idx, n, ctx)
     flags = (_redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0) |
-             (MX_TWO_LANES if two_lanes else 0) | (MX_REDC_KARATSUBA if kara_redc else 0))
+             (MX_TWO_LANES if two_lanes else 0) | (MX_REDC_KARATSUBA if kara_redc else 0) |
+             (MX_CHECK_INPUTS if check_inputs else 0))
     if n:  # one launch's workspace (0, a no-op, for arguments the call itself rejects)
         ctx.reserve(modexp_ws_bytes(ctx, n, window, flags=flags))
     _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,

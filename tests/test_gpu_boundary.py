@@ -134,3 +134,36 @@ def test_rsa_crt_with_caller_workspace(mx):
     assert ei.value.status == mx.MX_EINVAL
     ctx_p.close()
     ctx_q.close()
+
+
+def test_check_inputs_flag(mx):
+    """MX_CHECK_INPUTS: in-range inputs give the usual results; out-of-range ones give MX_EINVAL naming the count
+    and the first instance, with nothing else launched."""
+    import torch
+    bits, n = 1024, 100
+    mods = wl.random_moduli(wl.stream(43, "moduli"), bits, n)
+    ctx = mx.Context(mods, bits)
+    M = wl.words_to_ints(mods)
+    base = wl.random_below(wl.stream(43, "bases"), mods, bits)
+    e = mx.to_device(wl.random_exponents(wl.stream(43, "exps"), bits, n))
+    b = torch.from_numpy(wl.ints_to_words(base, ctx.words).view(np.int64)).cuda()
+    ref = mx.modexp(ctx, b, e, bits, window=4)
+    assert torch.equal(mx.modexp(ctx, b, e, bits, window=4, check_inputs=True), ref)
+    bad = list(base)
+    bad[17], bad[60] = M[17], M[60] + 5  # base = N and base > N
+    bb = torch.from_numpy(wl.ints_to_words(bad, ctx.words).view(np.int64)).cuda()
+    out = torch.zeros_like(bb)
+    with pytest.raises(mx.MontError) as ei:
+        mx.modexp(ctx, bb, e, bits, window=4, out=out, check_inputs=True)
+    assert ei.value.status == mx.MX_EINVAL and "2 of 100" in str(ei.value) and "instance 17" in str(ei.value)
+    assert torch.count_nonzero(out).item() == 0
+    # Montgomery operands: a, b < 2N
+    A = wl.random_below(wl.stream(43, "ops_a"), mods, bits, scale=2)
+    a = torch.from_numpy(wl.ints_to_words(A, ctx.mont_words).view(np.int64)).cuda()
+    assert torch.equal(mx.mont_mul(ctx, a, a, check_inputs=True), mx.mont_mul(ctx, a, a))
+    A[99] = 2 * M[99]
+    a2 = torch.from_numpy(wl.ints_to_words(A, ctx.mont_words).view(np.int64)).cuda()
+    with pytest.raises(mx.MontError) as ei:
+        mx.mont_sqr(ctx, a2, check_inputs=True)
+    assert ei.value.status == mx.MX_EINVAL and "1 of 100" in str(ei.value) and "instance 99" in str(ei.value)
+    ctx.close()
