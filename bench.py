@@ -393,6 +393,12 @@ def other_workloads(a, mx, counts, dev, stream):
                                              one_lane=True, stream=stream), 2, 1, stream)
     c3["modexp_per_s_schoolbook_one_lane"] = b3.n * 2 / wl_
     c3["schoolbook_vs_karatsuba_one_lane"] = c3["modexp_per_s_schoolbook_one_lane"] / c3["modexp_per_s_karatsuba"]
+    # the truncated q N by one-level Karatsuba in the block kernel (one lane per instance, row f2)
+    wl_, k = time_launches(lambda: mx.modexp(b3.ctx, b3.base, b3.exp, 4096, window=6, out=b3.out, block=True,
+                                             kara_redc=True, stream=stream), 2, 1, stream)
+    c3["modexp_per_s_kara_redc_one_lane"] = b3.n * 2 / wl_
+    c3["schoolbook_vs_kara_redc_one_lane"] = (c3["modexp_per_s_schoolbook_one_lane"] /
+                                              c3["modexp_per_s_kara_redc_one_lane"])
     # raw products at Table 6's largest sizes (limb counts 147 and 149), schoolbook and Karatsuba at one
     # and two levels, 16384 seeded instances each
     g = wl.stream(3, "ops_a")

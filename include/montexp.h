@@ -108,9 +108,12 @@ enum {
                           limb-wise half sums, so that every column is the
                           schoolbook's; same results.  Single operations and
                           exponentiation of the register-resident classes
-                          (<= 2048 bits), else MX_EUNSUPPORTED; with another
-                          MX_REDC_ flag, MX_EINVAL; not in the mixed launch
-                          or rsa_crt_batch                                   */
+                          (<= 2048 bits) and of the block kernels with an
+                          even block count (2048 with MX_IMPL_BLOCK or
+                          MX_MUL_KARATSUBA, 4096; one lane per instance,
+                          MX_TWO_LANES refused), else MX_EUNSUPPORTED; with
+                          another MX_REDC_ flag, MX_EINVAL; not in the mixed
+                          launch or rsa_crt_batch                            */
 };
 
 /* Montgomery contexts for `count` moduli of size class `bits` (Section 4:

@@ -291,6 +291,17 @@ __device__ __forceinline__ void blk_cols(uint64_t (&cols)[NC], const uint32_t (&
   });
 }
 
+// As blk_cols (no UPPER) with the multiply-add policy M.
+template <int H, int CLO, int CHI, typename M, int NC>
+__device__ __forceinline__ void blk_cols_m(uint64_t (&cols)[NC], const uint32_t (&a)[H], const uint32_t (&b)[H]) {
+  constexpr int BK = kColBlock;
+  sfor<0, (CHI - CLO + BK) / BK>([&](auto Bc) {
+    constexpr int k0 = CLO + decltype(Bc)::value * BK;
+    constexpr int bk = (CHI + 1 - k0) < BK ? (CHI + 1 - k0) : BK;
+    colblock<k0, bk, 0, H - 1, 0, H - 1, false, M>(a, b, *reinterpret_cast<uint64_t(*)[bk]>(&cols[k0]));
+  });
+}
+
 // Normalises cols[0 .. H-1] with the running carry into o, then moves the
 // high columns down by H (the next diagonal's window).
 template <int H>
@@ -496,6 +507,146 @@ __device__ __forceinline__ void scan_qn(const LaneBuf& ws, const LaneBuf& cn) {
   uint32_t o[H];
   blk_emit<H>(cols, carry, o);  // C < 2N < R: no carry remains
   st_rows<H>(ws, Lay::Y + (K - 1) * H, o);
+}
+
+// ---- truncated q N by one-level Karatsuba (Section 5, Karatsuba paragraph) ----
+//
+// Halves of M = K / 2 blocks: q = q0 + beta q1 and N = n0 + beta n1, beta = 2^(28 h), h = M H.  With
+// the half sums taken limb by limb, without carries (sq = q0 + q1 and sn = n0 + n1, 29-bit limbs),
+// column w of q N is
+//   D0[w] + (D1 - D0 - D2)[w - h] + D2[w - 2h],   D0 = q0 n0, D1 = sq sn, D2 = q1 n1,
+// which is the schoolbook column exactly, so scan_qn's two-column carry recovery applies unchanged.
+// Columns are summed modulo 2^64: a partial sum of D1 may pass 2^64 (up to h products of 29-bit
+// limbs), but every complete column of T + q N is below 2^64, so its sum modulo 2^64 is exact.
+// D2 enters twice, at w - h (subtracted) and w - 2h: its 2h - 1 column sums are formed once, into
+// the S rows (two 32-bit rows per column), and read back for both.  The middle term's block pairs
+// add sq sn and subtract q0 n0 (signed multiply-adds with the modulus words negated).  Products:
+// D2 whole (M^2 block products), the middle term's pairs on the anti-diagonal (high parts) and
+// above, twice, and single top products for column n - 2 -- the schoolbook's truncated count at one
+// level (Theorem 2; no saving, the identity is what two levels would build on).
+
+// raw column sums of D2 = q1 n1 into rows dst (column x in rows dst + 2x, dst + 2x + 1: low, high)
+template <int H, int M>
+__device__ __forceinline__ void scan_d2_raw(const LaneBuf& ws, uint32_t q1, const LaneBuf& cn, uint32_t n1,
+                                            uint32_t dst) {
+  uint64_t cols[2 * H];
+  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+#pragma nounroll
+  for (uint32_t c = 0; c + 1 < 2 * M; ++c) {
+    const uint32_t ilo = c >= M ? c - M + 1 : 0u, ihi = c < M ? c : M - 1;
+#pragma nounroll
+    for (uint32_t i = ilo; i <= ihi; ++i) {
+      uint32_t a[H], b[H];
+      ld_rows<H>(ws, q1 + i * H, a);
+      ld_rows<H>(cn, n1 + (c - i) * H, b);
+      compiler_fence();
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+      compiler_fence();
+    }
+    sfor<0, H>([&](auto D) {
+      constexpr int d = decltype(D)::value;
+      ws.st(dst + 2 * (c * H + d), (uint32_t)cols[d]);
+      ws.st(dst + 2 * (c * H + d) + 1, (uint32_t)(cols[d] >> 32));
+      cols[d] = cols[d + H];
+      cols[d + H] = 0;
+    });
+  }
+  sfor<0, H - 1>([&](auto D) {  // the last diagonal's high part: columns (2M - 1) H .. 2 M H - 2
+    constexpr int d = decltype(D)::value;
+    ws.st(dst + 2 * ((2 * M - 1) * H + d), (uint32_t)cols[d]);
+    ws.st(dst + 2 * ((2 * M - 1) * H + d) + 1, (uint32_t)(cols[d] >> 32));
+  });
+}
+
+template <int H, int K>
+__device__ __forceinline__ void scan_qn_kara(const LaneBuf& ws, const LaneBuf& cn) {
+  using Lay = BlkLayout<H, K>;
+  static_assert(K % 2 == 0, "the Karatsuba halves need an even block count");
+  constexpr uint32_t M = K / 2, h = M * H, n = Lay::n, ND2 = 2 * h - 1;
+  static_assert(2 * ND2 <= 2 * Lay::n + 1, "D2's column sums fit the S rows");
+  constexpr uint32_t D2 = Lay::S;
+  scan_d2_raw<H, M>(ws, Lay::Q + h, cn, h, D2);
+  auto d2 = [&](uint32_t x) -> uint64_t {  // column x of D2, 0 for x outside 0 .. 2h - 2
+    const bool in = x <= ND2 - 1;
+    const uint32_t r = D2 + 2 * (in ? x : 0u);
+    const uint64_t v = (uint64_t)ws.ld(r) | ((uint64_t)ws.ld(r + 1) << 32);
+    return in ? v : 0ull;
+  };
+  uint64_t cols[2 * H];
+  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  // column n - 2 (local H - 2 of output diagonal K - 1): the middle term's top products on its local
+  // diagonal M - 2, and D0's top product (D0[w] reaches no higher column)
+#pragma nounroll
+  for (uint32_t i = 0; i + 2 <= M; ++i) {
+    const uint32_t j = M - 2 - i, ri = i * H + H - 1, rj = j * H + H - 1;
+    const uint32_t a0 = ws.ld(Lay::Q + ri), a1 = ws.ld(Lay::Q + h + ri), b0 = cn.ld(rj), b1 = cn.ld(h + rj);
+    cols[H - 2] += (uint64_t)(a0 + a1) * (b0 + b1) - (uint64_t)a0 * b0;
+  }
+  cols[H - 2] += (uint64_t)ws.ld(Lay::Q + h - 1) * cn.ld(h - 1);
+  uint64_t carry = 0;
+#pragma nounroll
+  for (uint32_t b = K - 1; b + 1 < 2 * K; ++b) {
+    // the middle term's block pairs (i, j), i + j = b - M, of the M-block products
+    const uint32_t d = b - M, ilo = d >= M ? d - M + 1 : 0u, ihi = d < M ? d : M - 1;
+#pragma nounroll
+    for (uint32_t i = ilo; i <= ihi && i < M; ++i) {
+      const uint32_t j = d - i;
+      uint32_t q0[H], sq[H], n0[H], sn[H];
+      ld_rows<H>(ws, Lay::Q + i * H, q0);
+      ld_rows<H>(ws, Lay::Q + h + i * H, sq);
+      ld_rows<H>(cn, j * H, n0);
+      ld_rows<H>(cn, h + j * H, sn);
+      compiler_fence();
+      sfor<0, H>([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        sq[p] += q0[p];
+        sn[p] += n0[p];
+        n0[p] = 0u - n0[p];
+      });
+      if (b == K - 1) {  // the anti-diagonal: only its columns >= H - 2 reach column n - 2
+        blk_cols_m<H, H - 2, 2 * H - 2, PlainMad>(cols, sq, sn);
+        blk_cols_m<H, H - 2, 2 * H - 2, SignedMad>(cols, q0, n0);
+      } else {
+        blk_cols_m<H, 0, 2 * H - 2, PlainMad>(cols, sq, sn);
+        blk_cols_m<H, 0, 2 * H - 2, SignedMad>(cols, q0, n0);
+      }
+      compiler_fence();
+    }
+    // output block b is complete once T, -D2[w - h] and D2[w - 2h] are added (w = b H + k)
+    uint32_t tb[H];
+    ld_rows<H>(ws, Lay::T + b * H, tb);
+    sfor<0, H>([&](auto D) {
+      constexpr uint32_t k = decltype(D)::value;
+      const uint32_t w = b * H + k;
+      cols[k] += (uint64_t)tb[k] - d2(w - h) + d2(w - 2 * h);
+    });
+    if (b == K - 1) {
+      const uint64_t a2 = cols[H - 2];
+      const uint64_t a1 = cols[H - 1] + (a2 >> kLimbBits);
+      carry = (a1 >> kLimbBits) + ((((uint32_t)a1 | (uint32_t)a2) & kLimbMask) != 0u ? 1u : 0u);
+      sfor<0, H>([&](auto D) {
+        constexpr int dd = decltype(D)::value;
+        cols[dd] = cols[dd + H];
+        cols[dd + H] = 0;
+      });
+    } else {
+      uint32_t o[H];
+      blk_emit<H>(cols, carry, o);
+      st_rows<H>(ws, Lay::Y + (b - K) * H, o);
+    }
+    compiler_fence();
+  }
+  uint32_t tb[H];
+  ld_rows<H>(ws, Lay::T + (2 * K - 1) * H, tb);
+  sfor<0, H>([&](auto D) {
+    constexpr uint32_t k = decltype(D)::value;
+    const uint32_t w = (2 * K - 1) * H + k;
+    cols[k] += (uint64_t)tb[k] + d2(w - 2 * h);
+  });
+  uint32_t o[H];
+  blk_emit<H>(cols, carry, o);
+  st_rows<H>(ws, Lay::Y + (K - 1) * H, o);
+  (void)n;
 }
 
 // ---- several lanes per instance --------------------------------------------
@@ -754,9 +905,11 @@ __device__ __forceinline__ void scang_qn(const LaneBuf& ws, const LaneBuf& cn) {
 // One Montgomery product on the workspace: Y <- REDC(Y * B) or REDC(Y^2).
 // n = K H; context blocks come from the limb-major context arrays.  LP lanes
 // per instance (1, or 2 or 4 for the schoolbook product).
-template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1>
+// KREDC: the truncated q N by one-level Karatsuba (scan_qn_kara; one lane per instance, K even).
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false>
 __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const LaneBuf& cn, const LaneBuf& cnp) {
   static_assert(LP == 1 || ((LP == 2 || LP == 4) && !KARA), "several lanes per instance: schoolbook products only");
+  static_assert(!KREDC || (LP == 1 && TRUNC && K % 2 == 0), "Karatsuba-truncated q N: one lane, even block count");
   if constexpr (LP > 1) {
     scang_product<H, K, LP>(sqr, ws);
     scang_q<H, K, LP>(ws, cnp);
@@ -770,7 +923,10 @@ __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const Lane
     // ---- q = T_lo * N' mod R: pairs i + j <= K - 1 (Algorithm 6 step 1) ------
     scan_q<H, K>(ws, cnp);
     // ---- C = (T + q N) / R, truncated (Theorem 2) or whole (Algorithm 3) -----
-    scan_qn<H, K, TRUNC>(ws, cn);
+    if constexpr (KREDC)
+      scan_qn_kara<H, K>(ws, cn);
+    else
+      scan_qn<H, K, TRUNC>(ws, cn);
   }
 }
 
@@ -808,7 +964,7 @@ __device__ __forceinline__ void contract_rows(const LaneBuf& ws, uint32_t row, u
 }
 
 // ---- batched modmul / modsqr, block version ---------------------------------
-template <int H, int K, bool TRUNC, bool SQR, bool KARA = false>
+template <int H, int K, bool TRUNC, bool SQR, bool KARA = false, bool KREDC = false>
 __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                  const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
                                                  uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
@@ -829,7 +985,7 @@ __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __r
   const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
   expand_rows<H, K>(ws, Lay::Y, a + (size_t)inst * rw, rw);
   if (!SQR) expand_rows<H, K>(ws, Lay::B, b + (size_t)inst * rw, rw);
-  mont_blk<H, K, TRUNC, KARA>(SQR, ws, cn, cnp);
+  mont_blk<H, K, TRUNC, KARA, 1, KREDC>(SQR, ws, cn, cnp);
   if (live) contract_rows<H, K>(ws, Lay::Y, out + (size_t)inst * rw, rw);
 }
 
@@ -837,7 +993,7 @@ __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __r
 // A tile is 64 / LP instances (LP lanes per instance).  tws: this
 // wavefront's own workspace region (BlkLayout rows(w) rows of 64 / LP
 // instances, 256 / LP bytes per row), contiguous in memory.
-template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1>
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false>
 __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
                                                 const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                 uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
@@ -932,7 +1088,7 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
 #pragma nounroll
       for (uint32_t i = 0; i < n; ++i) ws.st(Lay::B + i, i == 0 ? 1u : 0u);
     }
-    mont_blk<H, K, TRUNC, KARA, LP>(kind == kSqr, ws, cn, cnp);
+    mont_blk<H, K, TRUNC, KARA, LP, KREDC>(kind == kSqr, ws, cn, cnp);
     if (store_e >= 0) copy_rows<H>(ws, Lay::G + (uint32_t)store_e * n, ws, Lay::Y, n);
   }
   // canonical result: subtract N once if Y >= N, in constant time: B = Y - N, then every limb of B
@@ -952,7 +1108,7 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
   if (writer) contract_rows<H, K>(ws, Lay::B, out + (size_t)inst * bw, bw);
 }
 
-template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1>
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false>
 __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                    const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                    uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
@@ -962,8 +1118,8 @@ __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* _
   const uint32_t tbytes = BlkLayout<H, K>::rows(w) * (256u / LP);  // this block's region
   if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // unreachable: the launcher checked ws
   stagger<H * K>(blockIdx.x, w);
-  modexp_tile_blk<H, K, TRUNC, KARA, LP>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
-                                         ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0);
+  modexp_tile_blk<H, K, TRUNC, KARA, LP, KREDC>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
+                                                ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0);
 }
 
 }  // namespace mx

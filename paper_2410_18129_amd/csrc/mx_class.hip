@@ -167,6 +167,20 @@ hipError_t mont_fn(int impl, int redc, bool sqr, const CtxDev& ctx, const uint32
   // every block's region must lie in ws: checked here, before anything is enqueued
   if ((uint64_t)ws_rows_fn(impl, false, 0) * 256u * blocks > ws_bytes) return hipErrorInvalidValue;
   if constexpr (kHasKara) {
+    // block kernels with the Karatsuba-truncated q N (one lane per instance); impl 2 also forms the
+    // product by Karatsuba
+    if (redc == kRedcKara && (kBlock || impl >= 1)) {
+#define MX_L(KA, S)                                                                                                 \
+  hipLaunchKernelGGL((k_mont_blk<kH, kK, true, S, KA, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, \
+                     count, ws, ws_bytes, coff)
+      if (impl == 2) {
+        if (sqr) MX_L(true, true); else MX_L(true, false);
+      } else {
+        if (sqr) MX_L(false, true); else MX_L(false, false);
+      }
+#undef MX_L
+      return hipGetLastError();
+    }
     if (impl == 2) {
 #define MX_L(T, S)                                                                                                \
   hipLaunchKernelGGL((k_mont_blk<kH, kK, T, S, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, a, b, out, count, \
@@ -227,6 +241,16 @@ hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx
   // 64-instance tile's): checked here, before anything is enqueued
   if ((uint64_t)ws_rows_fn(impl, true, w) * 256u * blocks > ws_bytes) return hipErrorInvalidValue;
   if constexpr (kHasKara) {
+    // block kernels with the Karatsuba-truncated q N: one lane per instance
+    if (redc == kRedcKara && (kBlock || impl >= 1)) {
+      if (impl == 2)
+        hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, true, 1, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base,
+                           ex, ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
+      else
+        hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, false, 1, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx,
+                           base, ex, ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
+      return hipGetLastError();
+    }
     if (impl == 2) {
       if (trunc)
         hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, true>), dim3(blocks), dim3(64), 0, st, ctx, cidx, base, ex,

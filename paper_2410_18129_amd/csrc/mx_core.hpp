@@ -74,6 +74,28 @@ struct PlainMad {
   }
 };
 
+// As PlainMad with both words read as signed 32-bit values (v_mad_i64_i32): with one of them negated
+// (0 - x), each step subtracts the product in wrapping 64-bit arithmetic.
+struct SignedMad {
+  template <int S>
+  __device__ __forceinline__ static void mac(uint64_t& acc, uint32_t a, uint32_t b) {
+    acc += (uint64_t)((int64_t)(int32_t)a * (int64_t)(int32_t)b);
+  }
+  __device__ __forceinline__ static void mad8(uint64_t (&acc)[8], uint32_t x0, uint32_t x1, uint32_t x2,
+                                              uint32_t x3, uint32_t x4, uint32_t x5, uint32_t x6, uint32_t x7,
+                                              uint32_t v) {
+    const int64_t sv = (int32_t)v;
+    acc[0] += (uint64_t)((int32_t)x0 * sv);
+    acc[1] += (uint64_t)((int32_t)x1 * sv);
+    acc[2] += (uint64_t)((int32_t)x2 * sv);
+    acc[3] += (uint64_t)((int32_t)x3 * sv);
+    acc[4] += (uint64_t)((int32_t)x4 * sv);
+    acc[5] += (uint64_t)((int32_t)x5 * sv);
+    acc[6] += (uint64_t)((int32_t)x6 * sv);
+    acc[7] += (uint64_t)((int32_t)x7 * sv);
+  }
+};
+
 #define MX_MAD_SDST(P, LO, HI)                                                                     \
   if constexpr ((S & 7) == P)                                                                      \
     asm("v_mad_u64_u32 %0, s[" #LO ":" #HI "], %1, %2, %0" : "+v"(acc) : "v"(a), "v"(b)           \

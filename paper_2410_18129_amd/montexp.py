@@ -267,7 +267,8 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
     one_lane: block kernels keep one lane per instance for small batches too (MX_ONE_LANE);
     two_lanes: at most two lanes per instance (MX_TWO_LANES).
     cios: word-interleaved Montgomery products (Algorithm 4, MX_REDC_CIOS; classes up to 2048 bits).
-    kara_redc: truncated high half of q N by one-level Karatsuba (MX_REDC_KARATSUBA; up to 2048 bits).
+    kara_redc: truncated high half of q N by one-level Karatsuba (MX_REDC_KARATSUBA; the register-resident
+    classes, and the block kernels at 2048 and 4096 bits with one lane per instance).
     check_inputs: check base < N first (MX_CHECK_INPUTS; the call then waits for the stream)."""
     n = base.shape[0]
     if out is None:

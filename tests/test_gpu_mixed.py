@@ -309,6 +309,41 @@ def test_karatsuba_matches_schoolbook(mx, bits):
     ctx.close()
 
 
+@pytest.mark.parametrize("bits", [2048, 4096])
+def test_block_karatsuba_truncated_reduction(mx, bits):
+    """The truncated q N by one-level Karatsuba in the block kernels (Section 5, Karatsuba paragraph): the
+    same integers as the schoolbook-truncated block kernels and the oracle, for products, squares and
+    exponentiations, with the schoolbook or the Karatsuba product."""
+    from tests.gpu_util import adversarial_pairs
+    n = 67
+    mods = wl.random_moduli(wl.stream(18, "moduli"), bits, n)
+    M = wl.words_to_ints(mods)
+    g = wl.stream(18, "ops_a")
+    A = wl.random_below(g, mods, bits, scale=2)
+    B = wl.random_below(g, mods, bits, scale=2)
+    for k, (x, y) in enumerate(adversarial_pairs(M[0], bits)):
+        A[k], B[k] = x % (2 * M[k]), y % (2 * M[k])
+    ctx = mx.Context(mods, bits)
+    a, b = ints_dev(A, ctx.mont_words), ints_dev(B, ctx.mont_words)
+    for impl in (True, "karatsuba"):
+        kmul = dev_ints(mx.mont_mul(ctx, a, b, block=impl, kara_redc=True))
+        ksqr = dev_ints(mx.mont_sqr(ctx, a, block=impl, kara_redc=True))
+        assert kmul == dev_ints(mx.mont_mul(ctx, a, b, block=True)), impl
+        assert ksqr == dev_ints(mx.mont_sqr(ctx, a, block=True)), impl
+    for i in range(n):
+        assert kmul[i] == oracle.montmul(A[i], B[i], M[i], ctx.r_bits), i
+        assert ksqr[i] == oracle.montmul(A[i], A[i], M[i], ctx.r_bits), i
+    base = wl.random_below_fast(wl.stream(18, "bases"), mods, bits)
+    exps = wl.random_exponents(wl.stream(18, "exps"), bits, n)
+    bd, ed = mx.to_device(base), mx.to_device(exps)
+    rk = dev_ints(mx.modexp(ctx, bd, ed, bits, window=4, block=True, kara_redc=True))
+    assert rk == dev_ints(mx.modexp(ctx, bd, ed, bits, window=4, block=True))
+    Bs, Es = wl.words_to_ints(base), wl.words_to_ints(exps)
+    for i in (0, n - 1):
+        assert rk[i] == oracle.modexp(Bs[i], Es[i], M[i], bits), i
+    ctx.close()
+
+
 @pytest.mark.parametrize("bits", [1024, 3072])
 def test_karatsuba_needs_even_block_count(mx, bits):
     ctx = mx.Context(wl.random_moduli(wl.stream(17, "moduli"), bits, 1), bits)

@@ -39,6 +39,7 @@ def _redcs(bits):
     r = {"trunc": {}, "plain": {"plain": True}}
     if bits <= 2048:
         r["cios"] = {"cios": True}
+    if bits != 3072:  # the block classes need an even block count (4096: four blocks of 37 limbs)
         r["kara"] = {"kara_redc": True}
     return r
 
@@ -298,9 +299,10 @@ def test_errors_and_noops(mx):
         with pytest.raises(mx.MontError) as ei:
             mx.mont_sqr(c, x, cios=True, block=block)
         assert ei.value.status == mx.MX_EUNSUPPORTED
-        with pytest.raises(mx.MontError) as ei:
-            mx.mont_mul(c, x, x, kara_redc=True, block=block)
-        assert ei.value.status == mx.MX_EUNSUPPORTED
+        if bits == 3072:  # an odd block count: no Karatsuba halves
+            with pytest.raises(mx.MontError) as ei:
+                mx.mont_mul(c, x, x, kara_redc=True, block=block)
+            assert ei.value.status == mx.MX_EUNSUPPORTED
         xb = torch.zeros((1, c.words), dtype=torch.int64, device="cuda")
         e1 = torch.zeros((1, 1), dtype=torch.int64, device="cuda")
         with pytest.raises(mx.MontError) as ei:
