@@ -649,56 +649,122 @@ __device__ __forceinline__ void scan_qn_kara(const LaneBuf& ws, const LaneBuf& c
   (void)n;
 }
 
-// ---- several lanes per instance --------------------------------------------
+// ---- several lanes per instance ----------------------------------------------
 //
 // For batches too small to give every SIMD a wavefront, LP = 2 or 4
-// consecutive lanes hold the same instance and cut its latency.  The block
-// pairs of each diagonal are dealt to the group's lanes in turn (a lane left
-// without a pair in a diagonal's last slot multiplies by zero); each lane
-// accumulates its own partial column sums, and when a diagonal's low columns
-// are emitted the partial sums are added across the group (DPP swaps inside
-// a quad of lanes), so all lanes of the group normalise the same totals and
-// write the same limbs.  Square blocks are formed as whole block products
-// here (another lane of the group may be running a cross pair in the same
-// instructions).
+// consecutive lanes hold the same instance and cut its latency.  The columns
+// of every diagonal are split among them by residue: lane r of a group forms
+// the local columns k = LP u + r (k = p + q over the limbs p of the first
+// block and q of the second) in its register cols[u].  It reads the first
+// operand block as is and the second shifted down by r, Br[m] = B[m + r] for
+// -LP < m < H (zero where m + r falls outside the block), so that its column
+// LP u + r is the sum over p of A[p] Br[LP u - p] with compile-time indices.
+// Every lane thus does a 1/LP share (plus a few products by zero) of every
+// block pair, and no partial sums are added across lanes.  When a diagonal's
+// low H columns are final, every lane reads each of them from the lane that
+// holds it (a DPP broadcast inside the group) and normalises the same limbs,
+// and the high columns move to the lanes that hold them in the next diagonal
+// (a DPP rotation by H mod LP, as H is not a multiple of LP).  Square blocks
+// are formed as whole block products here.
 
-// v + the same 64-bit variable of the other lanes of this lane's group of LP
-// consecutive lanes (LP = 1, 2 or 4)
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp_add64(uint64_t v) {
-  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
-  const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
-  return v + (((uint64_t)phi << 32) | plo);
+// for each lane i of a quad: the lane of its group of LP that it reads, S fixed (bcast) or own + S (rot)
+template <int LP, int S, bool ROT>
+constexpr int quad_ctrl() {
+  int ctrl = 0;
+  for (int i = 0; i < 4; ++i) {
+    const int g = i & ~(LP - 1);
+    const int src = g | ((ROT ? i + S : S) & (LP - 1));
+    ctrl |= src << (2 * i);
+  }
+  return ctrl;
 }
-template <int LP>
-__device__ __forceinline__ uint64_t group_sum(uint64_t v) {
-  static_assert(LP == 1 || LP == 2 || LP == 4, "lane groups of 1, 2 or 4");
-  if constexpr (LP >= 2) v = dpp_add64<0xB1>(v);  // quad_perm [1,0,3,2]: swap adjacent lanes
-  if constexpr (LP == 4) v = dpp_add64<0x4E>(v);  // quad_perm [2,3,0,1]: swap lane pairs
-  return v;
+template <int LP, int S, bool ROT>
+__device__ __forceinline__ uint64_t grp_read64(uint64_t v) {
+  constexpr int ctrl = quad_ctrl<LP, S, ROT>();
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, ctrl, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), ctrl, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
 }
 
-// blk_emit on the group's summed columns
 template <int H, int LP>
-__device__ __forceinline__ void blk_emitg(uint64_t (&cols)[2 * H], uint64_t& carry, uint32_t (&o)[H]) {
+struct Res {
+  static constexpr int NB = H + LP - 1;           // Br[m], m = -(LP - 1) .. H - 1, at index m + LP - 1
+  static constexpr int NU = (2 * H - 2) / LP + 1;  // registers for the local columns 0 .. 2H - 2
+};
+
+// Br of the block at rows row0 .. row0 + H - 1 of b, for this lane's r
+template <int H, int LP>
+__device__ __forceinline__ void ld_shift(const LaneBuf& b, uint32_t row0, uint32_t r, uint32_t (&x)[Res<H, LP>::NB]) {
+  const uint32_t vr = b.vo + r * b.ls;
+  sfor<0, Res<H, LP>::NB>([&](auto I) {
+    constexpr int m = (int)decltype(I)::value - (LP - 1);
+    if constexpr (m >= 0 && m + LP - 1 <= H - 1) {
+      x[decltype(I)::value] = bload(b.r, vr, (row0 + (uint32_t)m) * b.ls);  // m + r < H for every r
+    } else {
+      const int q = m + (int)r;
+      const bool in = q >= 0 && q <= H - 1;
+      const uint32_t v = bload(b.r, b.vo + (uint32_t)(in ? q : 0) * b.ls, row0 * b.ls);
+      x[decltype(I)::value] = in ? v : 0u;
+    }
+  });
+}
+
+// cols[u] += sum over p of a[p] Br[LP u - p] for the registers ULO .. UHI, eight at a time
+template <int H, int LP, int ULO, int UHI, int NU>
+__device__ __forceinline__ void res_cols(uint64_t (&cols)[NU], const uint32_t (&a)[H],
+                                         const uint32_t (&bs)[Res<H, LP>::NB]) {
+  constexpr int BK = kColBlock;
+  sfor<0, (UHI - ULO + BK) / BK>([&](auto Bc) {
+    constexpr int u0 = ULO + decltype(Bc)::value * BK;
+    constexpr int bk = (UHI + 1 - u0) < BK ? (UHI + 1 - u0) : BK;
+    sfor<0, H>([&](auto P) {
+      constexpr int p = decltype(P)::value;
+      sfor<0, bk>([&](auto D) {
+        constexpr int u = u0 + decltype(D)::value;
+        constexpr int m = LP * u - p;
+        if constexpr (m >= -(LP - 1) && m <= H - 1) cols[u] += (uint64_t)a[p] * bs[m + LP - 1];
+      });
+    });
+  });
+}
+
+// The diagonal's low H columns, normalised with the running carry into o (every lane of the group alike).
+template <int H, int LP, int NU>
+__device__ __forceinline__ void res_emit(const uint64_t (&cols)[NU], uint64_t& carry, uint32_t (&o)[H]) {
   sfor<0, H>([&](auto D) {
-    constexpr int d = decltype(D)::value;
-    const uint64_t v = group_sum<LP>(cols[d]) + carry;
-    o[d] = (uint32_t)v & kLimbMask;
+    constexpr int k = decltype(D)::value;
+    const uint64_t v = grp_read64<LP, k % LP, false>(cols[k / LP]) + carry;
+    o[k] = (uint32_t)v & kLimbMask;
     carry = v >> kLimbBits;
   });
-  sfor<0, H>([&](auto D) {
-    constexpr int d = decltype(D)::value;
-    cols[d] = cols[d + H];
-    cols[d + H] = 0;
-  });
 }
 
-// This lane's view of block `blk` of an array: row r of the result is row
-// blk H + r of the array.
-__device__ __forceinline__ LaneBuf blk_view(const LaneBuf& b, uint32_t blk, uint32_t h) {
-  return LaneBuf{b.r, b.vo + blk * h * b.ls, b.ls};
+// The high columns H .. 2H - 2 become the next diagonal's columns 0 .. H - 2: lane r' takes column
+// LP u' + r' + H from lane (r' + H) mod LP, register u' + (r' + H) / LP; every other register is cleared.
+template <int H, int LP, int NU>
+__device__ __forceinline__ void res_roll(uint64_t (&cols)[NU], uint32_t r) {
+  constexpr int h0 = H % LP, q0 = H / LP;
+  constexpr int NUP = (H - 2) / LP + 1;  // registers of the columns 0 .. H - 2
+  static_assert(NUP + q0 <= NU, "rolled registers");
+  const bool wrap = r + h0 >= (uint32_t)LP;
+  uint64_t nx[NUP];
+  sfor<0, NUP>([&](auto U) {
+    constexpr int u = decltype(U)::value;
+    const uint64_t x0 = grp_read64<LP, h0, true>(cols[u + q0]);
+    if constexpr (u + q0 + 1 < NU) {
+      const uint64_t x1 = grp_read64<LP, h0, true>(cols[u + q0 + 1]);
+      nx[u] = wrap ? x1 : x0;
+    } else {
+      nx[u] = wrap ? 0ull : x0;
+    }
+  });
+  sfor<0, NU>([&](auto U) {
+    constexpr int u = decltype(U)::value;
+    if constexpr (u < NUP)
+      cols[u] = nx[u];
+    else
+      cols[u] = 0;
+  });
 }
 
 // Pairs (i, c - i) of diagonal c, i >= ilo: their count, for the product
@@ -715,56 +781,50 @@ __device__ __forceinline__ uint32_t diag_pairs(uint32_t c, bool sqr) {
 template <int H, int K, int LP>
 __device__ __forceinline__ void scang_product(bool sqr, const LaneBuf& ws) {
   using Lay = BlkLayout<H, K>;
+  constexpr int NB = Res<H, LP>::NB, NU = Res<H, LP>::NU;
   const uint32_t rb = sqr ? Lay::Y : Lay::B;
   const uint32_t r = threadIdx.x % LP;
-  uint64_t cols[2 * H];
-  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  uint64_t cols[NU];
+  sfor<0, NU>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
-  // slot s of diagonal c: this lane's pair is i = ilo + LP s + r, if it exists
-  auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[H], uint32_t& sh, bool& valid) {
-    const uint32_t k = LP * s + r;
-    valid = k < diag_pairs<K>(c, sqr);
-    const uint32_t i = diag_ilo<K>(c) + (valid ? k : 0u), j = c - i;
-    ld_rows<H>(blk_view(ws, i, H), Lay::Y, x);
-    ld_rows<H>(blk_view(ws, j, H), rb, y);
+  auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[NB], uint32_t& sh) {
+    const uint32_t i = diag_ilo<K>(c) + s, j = c - i;
+    ld_rows<H>(ws, Lay::Y + i * H, x);
+    ld_shift<H, LP>(ws, rb + j * H, r, y);
     sh = sqr && i < j ? 1u : 0u;  // cross pairs of a square count twice
   };
-  uint32_t a[H], b[H], sh;
-  bool valid;
-  load(0, 0, a, b, sh, valid);
+  uint32_t a[H], b[NB], sh;
+  load(0, 0, a, b, sh);
   uint32_t c = 0, s = 0;
 #pragma nounroll
   for (;;) {
     uint32_t nc = c, ns = s + 1;
-    if (LP * ns >= diag_pairs<K>(c, sqr)) {
+    if (ns >= diag_pairs<K>(c, sqr)) {
       nc = c + 1;
       ns = 0;
     }
     const bool more = nc < 2 * K - 1;
-    uint32_t na[H], nb[H], nsh = 0;
-    bool nvalid = false;
-    if (more) load(nc, ns, na, nb, nsh, nvalid);
+    uint32_t na[H], nb[NB], nsh = 0;
+    if (more) load(nc, ns, na, nb, nsh);
     compiler_fence();
-    sfor<0, H>([&](auto P) { b[decltype(P)::value] = valid ? b[decltype(P)::value] << sh : 0u; });
-    blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
-    if (nc != c) {
+    sfor<0, NB>([&](auto P) { b[decltype(P)::value] <<= sh; });
+    res_cols<H, LP, 0, NU - 1>(cols, a, b);
+    if (nc != c) {  // diagonal c done: block c of T is final
       uint32_t o[H];
-      blk_emitg<H, LP>(cols, carry, o);
+      res_emit<H, LP>(cols, carry, o);
       st_rows<H>(ws, Lay::T + c * H, o);
+      res_roll<H, LP>(cols, r);
     }
     compiler_fence();
     if (!more) break;
     c = nc;
     s = ns;
     sh = nsh;
-    valid = nvalid;
-    sfor<0, H>([&](auto P) {
-      a[decltype(P)::value] = na[decltype(P)::value];
-      b[decltype(P)::value] = nb[decltype(P)::value];
-    });
+    sfor<0, H>([&](auto P) { a[decltype(P)::value] = na[decltype(P)::value]; });
+    sfor<0, NB>([&](auto P) { b[decltype(P)::value] = nb[decltype(P)::value]; });
   }
   uint32_t o[H];
-  blk_emitg<H, LP>(cols, carry, o);
+  res_emit<H, LP>(cols, carry, o);
   st_rows<H>(ws, Lay::T + (2 * K - 1) * H, o);
   ws.st(Lay::T + 2 * Lay::n, (uint32_t)carry);
 }
@@ -772,133 +832,126 @@ __device__ __forceinline__ void scang_product(bool sqr, const LaneBuf& ws) {
 template <int H, int K, int LP>
 __device__ __forceinline__ void scang_q(const LaneBuf& ws, const LaneBuf& cnp) {
   using Lay = BlkLayout<H, K>;
+  constexpr int NB = Res<H, LP>::NB, NU = Res<H, LP>::NU;
   const uint32_t r = threadIdx.x % LP;
-  uint64_t cols[2 * H];
-  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  uint64_t cols[NU];
+  sfor<0, NU>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
-  auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[H], bool& valid) {
-    const uint32_t k = LP * s + r;
-    valid = k <= c;
-    const uint32_t i = valid ? k : 0u;
-    ld_rows<H>(blk_view(ws, i, H), Lay::T, x);
-    ld_rows<H>(blk_view(cnp, c - i, H), 0, y);
+  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[NB]) {
+    ld_rows<H>(ws, Lay::T + i * H, x);
+    ld_shift<H, LP>(cnp, (c - i) * H, r, y);
   };
-  uint32_t a[H], b[H];
-  bool valid;
-  load(0, 0, a, b, valid);
-  uint32_t c = 0, s = 0;
+  uint32_t a[H], b[NB];
+  load(0, 0, a, b);
+  uint32_t c = 0, i = 0;
 #pragma nounroll
   for (;;) {
-    uint32_t nc = c, ns = s + 1;
-    if (LP * ns > c) {
+    uint32_t nc = c, ni = i + 1;
+    if (ni > c) {
       nc = c + 1;
-      ns = 0;
+      ni = 0;
     }
     const bool more = nc < K;
-    uint32_t na[H], nb[H];
-    bool nvalid = false;
-    if (more) load(nc, ns, na, nb, nvalid);
+    uint32_t na[H], nb[NB];
+    if (more) load(nc, ni, na, nb);
     compiler_fence();
-    sfor<0, H>([&](auto P) { b[decltype(P)::value] = valid ? b[decltype(P)::value] : 0u; });
     if (c + 1 < K)
-      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
-    else
-      blk_cols<H, 0, H - 1, false>(cols, a, b);
+      res_cols<H, LP, 0, NU - 1>(cols, a, b);
+    else  // the anti-diagonal: its low H columns (a few more in some lanes, never read)
+      res_cols<H, LP, 0, (H - 1) / LP>(cols, a, b);
     if (nc != c) {
       uint32_t o[H];
-      blk_emitg<H, LP>(cols, carry, o);  // the carry out of block K-1 is dropped: mod R
+      res_emit<H, LP>(cols, carry, o);  // the carry out of block K-1 is dropped: mod R
       st_rows<H>(ws, Lay::Q + c * H, o);
+      if (more) res_roll<H, LP>(cols, r);
     }
     compiler_fence();
     if (!more) break;
     c = nc;
-    s = ns;
-    valid = nvalid;
-    sfor<0, H>([&](auto P) {
-      a[decltype(P)::value] = na[decltype(P)::value];
-      b[decltype(P)::value] = nb[decltype(P)::value];
-    });
+    i = ni;
+    sfor<0, H>([&](auto P) { a[decltype(P)::value] = na[decltype(P)::value]; });
+    sfor<0, NB>([&](auto P) { b[decltype(P)::value] = nb[decltype(P)::value]; });
   }
+}
+
+// cols += block c of T, each lane its own columns k = LP u + r < H
+template <int H, int LP, int NU>
+__device__ __forceinline__ void res_add_rows(uint64_t (&cols)[NU], const LaneBuf& ws, uint32_t row0, uint32_t r) {
+  const uint32_t vr = ws.vo + r * ws.ls;
+  sfor<0, (H - 1) / LP + 1>([&](auto U) {
+    constexpr int u = decltype(U)::value;
+    const uint32_t t = bload(ws.r, vr, (row0 + (uint32_t)(LP * u)) * ws.ls);
+    if constexpr (LP * u + LP - 1 <= H - 1)
+      cols[u] += t;
+    else
+      cols[u] += (uint32_t)(LP * u) + r <= (uint32_t)(H - 1) ? t : 0u;
+  });
 }
 
 template <int H, int K, bool TRUNC, int LP>
 __device__ __forceinline__ void scang_qn(const LaneBuf& ws, const LaneBuf& cn) {
   using Lay = BlkLayout<H, K>;
+  constexpr int NB = Res<H, LP>::NB, NU = Res<H, LP>::NU;
   const uint32_t r = threadIdx.x % LP;
-  const uint32_t tmask = r == 0u ? 0xFFFFFFFFu : 0u;  // T is added in one lane of the group
-  uint64_t cols[2 * H];
-  sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+  uint64_t cols[NU];
+  sfor<0, NU>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
   constexpr uint32_t c0 = TRUNC ? K - 1 : 0;
+  static_assert(H - 1 - LP >= 0, "blocks of at least LP + 1 limbs");
   if constexpr (TRUNC && K >= 2) {
+    // the top products of diagonal K-2 (global column n-2 = local column H-2 of diagonal K-1), in the
+    // lane that holds that column
+    const uint32_t own = r == (uint32_t)((H - 2) % LP) ? 0xFFFFFFFFu : 0u;
 #pragma nounroll
     for (uint32_t i = 0; i + 2 <= K; ++i)
-      cols[H - 2] += (uint64_t)(ws.ld(Lay::Q + i * H + H - 1) & tmask) * cn.ld((K - 2 - i) * H + H - 1);
+      cols[(H - 2) / LP] += (uint64_t)(ws.ld(Lay::Q + i * H + H - 1) & own) * cn.ld((K - 2 - i) * H + H - 1);
   }
-  auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[H], bool& valid) {
-    const uint32_t k = LP * s + r;
-    valid = k < diag_pairs<K>(c, false);
-    const uint32_t i = diag_ilo<K>(c) + (valid ? k : 0u);
-    ld_rows<H>(blk_view(ws, i, H), Lay::Q, x);
-    ld_rows<H>(blk_view(cn, c - i, H), 0, y);
+  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[NB]) {
+    ld_rows<H>(ws, Lay::Q + i * H, x);
+    ld_shift<H, LP>(cn, (c - i) * H, r, y);
   };
-  uint32_t a[H], b[H];
-  bool valid;
-  load(c0, 0, a, b, valid);
-  uint32_t c = c0, s = 0;
+  uint32_t a[H], b[NB];
+  uint32_t c = c0, i = diag_ilo<K>(c0);
+  load(c, i, a, b);
 #pragma nounroll
   for (;;) {
-    uint32_t nc = c, ns = s + 1;
-    if (LP * ns >= diag_pairs<K>(c, false)) {
+    uint32_t nc = c, ni = i + 1;
+    if (ni > (c < K ? c : K - 1)) {
       nc = c + 1;
-      ns = 0;
+      ni = diag_ilo<K>(nc);
     }
     const bool more = nc < 2 * K - 1;
-    uint32_t na[H], nb[H];
-    bool nvalid = false;
-    if (more) load(nc, ns, na, nb, nvalid);
+    uint32_t na[H], nb[NB];
+    if (more) load(nc, ni, na, nb);
     compiler_fence();
-    sfor<0, H>([&](auto P) { b[decltype(P)::value] = valid ? b[decltype(P)::value] : 0u; });
-    if (TRUNC && c == K - 1)
-      blk_cols<H, H - 2, 2 * H - 2, false>(cols, a, b);
+    if (TRUNC && c == K - 1)  // columns >= H-2 (a few lower ones in some lanes, never read)
+      res_cols<H, LP, (H - 1 - LP) / LP, NU - 1>(cols, a, b);
     else
-      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+      res_cols<H, LP, 0, NU - 1>(cols, a, b);
     if (nc != c) {  // diagonal c done: add block c of T, then emit or fold the carry
-      uint32_t tb[H];
-      ld_rows<H>(ws, Lay::T + c * H, tb);
-      sfor<0, H>([&](auto D) { cols[decltype(D)::value] += tb[decltype(D)::value] & tmask; });
-      uint32_t o[H];
+      res_add_rows<H, LP>(cols, ws, Lay::T + c * H, r);
       if (TRUNC && c == K - 1) {
-        const uint64_t a2 = group_sum<LP>(cols[H - 2]);
-        const uint64_t a1 = group_sum<LP>(cols[H - 1]) + (a2 >> kLimbBits);
+        const uint64_t a2 = grp_read64<LP, (H - 2) % LP, false>(cols[(H - 2) / LP]);
+        const uint64_t a1 = grp_read64<LP, (H - 1) % LP, false>(cols[(H - 1) / LP]) + (a2 >> kLimbBits);
         carry = (a1 >> kLimbBits) + ((((uint32_t)a1 | (uint32_t)a2) & kLimbMask) != 0u ? 1u : 0u);
-        sfor<0, H>([&](auto D) {
-          constexpr int d = decltype(D)::value;
-          cols[d] = cols[d + H];
-          cols[d + H] = 0;
-        });
-      } else if (c < K) {  // PLAIN, low columns: they vanish mod 2^28
-        blk_emitg<H, LP>(cols, carry, o);
       } else {
-        blk_emitg<H, LP>(cols, carry, o);
-        st_rows<H>(ws, Lay::Y + (c - K) * H, o);
+        uint32_t o[H];
+        res_emit<H, LP>(cols, carry, o);
+        if (c >= K) st_rows<H>(ws, Lay::Y + (c - K) * H, o);  // PLAIN, c < K: the low columns vanish mod 2^28
       }
+      res_roll<H, LP>(cols, r);
     }
     compiler_fence();
     if (!more) break;
     c = nc;
-    s = ns;
-    valid = nvalid;
-    sfor<0, H>([&](auto P) {
-      a[decltype(P)::value] = na[decltype(P)::value];
-      b[decltype(P)::value] = nb[decltype(P)::value];
-    });
+    i = ni;
+    sfor<0, H>([&](auto P) { a[decltype(P)::value] = na[decltype(P)::value]; });
+    sfor<0, NB>([&](auto P) { b[decltype(P)::value] = nb[decltype(P)::value]; });
   }
-  uint32_t tb[H];
-  ld_rows<H>(ws, Lay::T + (2 * K - 1) * H, tb);
-  sfor<0, H>([&](auto D) { cols[decltype(D)::value] += tb[decltype(D)::value] & tmask; });
+  // the top block: columns (2K-1) H .. 2n-1 and T's top limbs
+  res_add_rows<H, LP>(cols, ws, Lay::T + (2 * K - 1) * H, r);
   uint32_t o[H];
-  blk_emitg<H, LP>(cols, carry, o);
+  res_emit<H, LP>(cols, carry, o);  // C < 2N < R: no carry remains
   st_rows<H>(ws, Lay::Y + (K - 1) * H, o);
 }
 
