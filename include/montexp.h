@@ -96,6 +96,12 @@ enum {
                           and throughput for a moderately loaded device; with
                           MX_ONE_LANE, MX_EINVAL; same results               */
   MX_MUL_KARATSUBA2 = 128, /* mp_mul_batch only: Karatsuba at two levels         */
+  MX_FOUR_LANES = 512, /* exponentiation with the block schoolbook kernels: four
+                          lanes per instance at any batch size (the default
+                          only up to 16384), the lanes' arrays in LDS; in the
+                          mixed launch, 3072- and 4096-bit tiles of 16
+                          instances; with MX_ONE_LANE or MX_TWO_LANES,
+                          MX_EINVAL; same results                            */
   MX_CHECK_INPUTS = 256, /* debugging: before the work, check the device-data
                           preconditions (a, b < 2N for mont_mul_batch and
                           mont_sqr_batch; base < N for the modexp_batch calls)

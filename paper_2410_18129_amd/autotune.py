@@ -31,17 +31,19 @@ from . import workload as wl
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "montexp", "plan_cache.json")
 FAMILY = {0: "register", mx.MX_IMPL_BLOCK: "block", mx.MX_MUL_KARATSUBA: "karatsuba"}
 # (window, flags) candidates per class; windows whose per-wave workspaces fit the plan's 2 GiB limit
-_B, _K, _1, _2 = mx.MX_IMPL_BLOCK, mx.MX_MUL_KARATSUBA, mx.MX_ONE_LANE, mx.MX_TWO_LANES
+_B, _K, _1, _2, _4 = mx.MX_IMPL_BLOCK, mx.MX_MUL_KARATSUBA, mx.MX_ONE_LANE, mx.MX_TWO_LANES, mx.MX_FOUR_LANES
 CANDIDATES = {
     1024: [(w, f) for f in (0, _B) for w in (3, 4, 5)],
     2048: [(w, f) for f in (0, _B, _K) for w in (3, 4, 5)],
-    3072: [(w, f) for f in (_B | _1, _B | _2) for w in (4, 5)],
-    4096: [(w, f) for f in (_B | _1, _B | _2, _K) for w in (4, 5)],
+    3072: [(w, f) for f in (_B | _1, _B | _2, _B | _4) for w in (4, 5)],
+    4096: [(w, f) for f in (_B | _1, _B | _2, _B | _4, _K) for w in (4, 5)],
 }
 
 
 def lanes_of(bits, flags):
     """Lanes per instance of a schedule (the plan's rule: two for 4096-bit schoolbook tiles by default)."""
+    if flags & mx.MX_FOUR_LANES:
+        return 4
     if flags & mx.MX_TWO_LANES:
         return 2
     if flags & (mx.MX_ONE_LANE | mx.MX_MUL_KARATSUBA) or bits != 4096:

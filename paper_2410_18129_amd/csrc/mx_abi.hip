@@ -160,12 +160,19 @@ struct WsTurn {
   hipError_t done() { return hipEventRecord(ctx->ws_done, st); }
 };
 
+// More than one of MX_ONE_LANE, MX_TWO_LANES and MX_FOUR_LANES.
+static bool lane_flags_conflict(uint32_t flags) {
+  const uint32_t l = flags & (uint32_t)(MX_ONE_LANE | MX_TWO_LANES | MX_FOUR_LANES);
+  return (l & (l - 1)) != 0;
+}
+
 // Kernel family for the flags: 0 register-resident, 1 block, 2 block + Karatsuba, 3 block with one
 // lane per instance whatever the batch size (MX_ONE_LANE), 4 block with at most two lanes per
-// instance (MX_TWO_LANES); -1 if not built.
+// instance (MX_TWO_LANES), 5 block with four lanes per instance at any batch size (MX_FOUR_LANES);
+// -1 if not built.
 static int impl_of(const mont_ctx* ctx, uint32_t flags) {
   if (flags & MX_MUL_KARATSUBA) return ctx->ops->has_kara ? 2 : -1;
-  const int blk = (flags & MX_ONE_LANE) ? 3 : (flags & MX_TWO_LANES) ? 4 : 1;
+  const int blk = (flags & MX_ONE_LANE) ? 3 : (flags & MX_TWO_LANES) ? 4 : (flags & MX_FOUR_LANES) ? 5 : 1;
   if (flags & MX_IMPL_BLOCK) return ctx->ops->has_block ? blk : -1;
   return ctx->bits > 2048 && blk != 1 ? blk : 0;
 }
@@ -189,7 +196,7 @@ static mx_status check_redc(const char* name, const mont_ctx* ctx, int impl, int
   if (redc == mx::kRedcKara) {
     const bool reg = impl == 0 && ctx->ops->has_cios;
     // block kernels (the only ones above 2048 bits), one lane per instance, an even block count
-    const bool blk = (impl >= 1 || ctx->bits > 2048) && impl != 4 && ctx->ops->has_kara;
+    const bool blk = (impl >= 1 || ctx->bits > 2048) && impl != 4 && impl != 5 && ctx->ops->has_kara;
     if (!reg && !blk)
       return fail(MX_EUNSUPPORTED, "%s: MX_REDC_KARATSUBA is built for the register-resident kernels and the block "
                   "kernels with an even block count (2048, 4096 bits), one lane per instance", name);
@@ -463,10 +470,10 @@ static mx_status modexp_args(const char* name, const mont_ctx* ctx, const uint32
   if (!ctx) return fail(MX_EINVAL, "%s: ctx is NULL", name);
   if (n && (!base || !out || (exp_bits && !exp))) return fail(MX_EINVAL, "%s: NULL operand pointer", name);
   if (flags & ~(uint32_t)(MX_REDC_PLAIN | MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_REDC_CIOS |
-                          MX_TWO_LANES | MX_REDC_KARATSUBA | MX_CHECK_INPUTS))
+                          MX_TWO_LANES | MX_REDC_KARATSUBA | MX_CHECK_INPUTS | MX_FOUR_LANES))
     return fail(MX_EINVAL, "%s: unknown flags 0x%x", name, flags);
-  if ((flags & MX_ONE_LANE) && (flags & MX_TWO_LANES))
-    return fail(MX_EINVAL, "%s: MX_ONE_LANE and MX_TWO_LANES exclude each other", name);
+  if (lane_flags_conflict(flags))
+    return fail(MX_EINVAL, "%s: MX_ONE_LANE, MX_TWO_LANES and MX_FOUR_LANES exclude each other", name);
   *impl = impl_of(ctx, flags);
   if (*impl < 0) return fail(MX_EUNSUPPORTED, "%s: kernel family not built for the %u-bit class", name, ctx->bits);
   *redc = redc_of(flags);

@@ -38,21 +38,34 @@ struct BlkLayout {
   static constexpr uint32_t rows(uint32_t w) { return G + (w ? (1u << w) * (uint32_t)n : 0u); }
 };
 
-// This lane's view of a limb-major array: row r at byte r * ls + vo.
+// This lane's view of a limb-major array: row r at byte r * ls + vo.  ldx / stx: row + x for a
+// per-lane x (the row itself the same in every lane).
 struct LaneBuf {
   __amdgpu_buffer_rsrc_t r;
   uint32_t vo;
   uint32_t ls;
   __device__ __forceinline__ uint32_t ld(uint32_t row) const { return bload(r, vo, row * ls); }
   __device__ __forceinline__ void st(uint32_t row, uint32_t v) const { bstore(r, v, vo, row * ls); }
+  __device__ __forceinline__ uint32_t ldx(uint32_t row, uint32_t x) const { return bload(r, vo + x * ls, row * ls); }
+  __device__ __forceinline__ void stx(uint32_t row, uint32_t x, uint32_t v) const { bstore(r, v, vo + x * ls, row * ls); }
 };
 
-template <int M>
-__device__ __forceinline__ void ld_rows(const LaneBuf& b, uint32_t row, uint32_t (&x)[M]) {
+// The same view of an array in LDS: p is this lane's word of row 0, ls words between rows.
+struct LdsBuf {
+  uint32_t* p;
+  uint32_t ls;
+  __device__ __forceinline__ uint32_t ld(uint32_t row) const { return p[row * ls]; }
+  __device__ __forceinline__ void st(uint32_t row, uint32_t v) const { p[row * ls] = v; }
+  __device__ __forceinline__ uint32_t ldx(uint32_t row, uint32_t x) const { return p[(row + x) * ls]; }
+  __device__ __forceinline__ void stx(uint32_t row, uint32_t x, uint32_t v) const { p[(row + x) * ls] = v; }
+};
+
+template <int M, typename Buf>
+__device__ __forceinline__ void ld_rows(const Buf& b, uint32_t row, uint32_t (&x)[M]) {
   sfor<0, M>([&](auto I) { x[decltype(I)::value] = b.ld(row + decltype(I)::value); });
 }
-template <int M>
-__device__ __forceinline__ void st_rows(const LaneBuf& b, uint32_t row, const uint32_t (&x)[M]) {
+template <int M, typename Buf>
+__device__ __forceinline__ void st_rows(const Buf& b, uint32_t row, const uint32_t (&x)[M]) {
   sfor<0, M>([&](auto I) { b.st(row + decltype(I)::value, x[decltype(I)::value]); });
 }
 // rows[row + i] += mult * p[i] (redundant limbs, no carries)
@@ -101,9 +114,8 @@ __device__ __forceinline__ uint64_t norm_rows(const LaneBuf& b, uint32_t row, ui
 
 // rows[dst + i] = rows[src + i] for i < len, C limbs per register batch, the
 // next batch read before the current one is written.
-template <int C>
-__device__ __forceinline__ void copy_rows(const LaneBuf& d, uint32_t dst, const LaneBuf& sb, uint32_t src,
-                                          uint32_t len) {
+template <int C, typename DB, typename SB>
+__device__ __forceinline__ void copy_rows(const DB& d, uint32_t dst, const SB& sb, uint32_t src, uint32_t len) {
   uint32_t i = 0;
   uint32_t x[C];
   if (len >= C) ld_rows<C>(sb, src, x);
@@ -280,14 +292,15 @@ __device__ __forceinline__ void kara_product(bool sqr, const LaneBuf& ws) {
 // loads its two operand blocks one pair ahead (the reads overlap the previous
 // pair's products); nothing is read back from the workspace.
 
-// cols[L] += sum over a[i] b[j] with i + j = L, CLO <= L <= CHI (and i > j when UPPER).
-template <int H, int CLO, int CHI, bool UPPER, int NC>
+// cols[L] += sum over a[i] b[j] with i + j = L, CLO <= L <= CHI (and i > j when UPPER), products
+// issued by the policy M.
+template <int H, int CLO, int CHI, bool UPPER, typename M = PlainMad, int NC>
 __device__ __forceinline__ void blk_cols(uint64_t (&cols)[NC], const uint32_t (&a)[H], const uint32_t (&b)[H]) {
   constexpr int BK = kColBlock;
   sfor<0, (CHI - CLO + BK) / BK>([&](auto Bc) {
     constexpr int k0 = CLO + decltype(Bc)::value * BK;
     constexpr int bk = (CHI + 1 - k0) < BK ? (CHI + 1 - k0) : BK;
-    colblock<k0, bk, 0, H - 1, 0, H - 1, UPPER, PlainMad>(a, b, *reinterpret_cast<uint64_t(*)[bk]>(&cols[k0]));
+    colblock<k0, bk, 0, H - 1, 0, H - 1, UPPER, M>(a, b, *reinterpret_cast<uint64_t(*)[bk]>(&cols[k0]));
   });
 }
 
@@ -319,6 +332,53 @@ __device__ __forceinline__ void blk_emit(uint64_t (&cols)[2 * H], uint64_t& carr
   });
 }
 
+// Makes every word of x count as produced here (an empty asm per word): the reads that fill x are
+// waited for at this point, and nothing computed from x is moved above it.
+template <int I, int N>
+__device__ __forceinline__ void pin_word(uint32_t (&x)[N]) {
+  asm volatile("" : "+v"(x[I]));
+}
+template <int N>
+__device__ __forceinline__ void pin_words(uint32_t (&x)[N]) {
+  sfor<0, N>([&](auto I) { pin_word<decltype(I)::value>(x); });
+}
+
+// The block pairs of one phase, in order: pair p is multiplied while pair p + 1 is read, into the other
+// of two register sets, so that nothing is copied between iterations.  next(c, s, nc, ns) gives the
+// pair after (c, s) and whether there is one; load(c, s, x, y) reads a pair's blocks; body(c, s, nc,
+// more, x, y) multiplies them (and emits when nc != c).  The current pair's words are pinned before
+// the next pair's reads are issued: the compiler's wait for them (which it may not count exactly
+// across the loop) then cannot also wait for the reads just issued.
+template <int NA, int NB, typename Next, typename Load, typename Body>
+__device__ __forceinline__ void run_pairs(uint32_t c, uint32_t s, Next&& next, Load&& load, Body&& body) {
+  uint32_t a0[NA], b0[NB], a1[NA], b1[NB];
+  load(c, s, a0, b0);
+#pragma nounroll
+  for (;;) {
+    uint32_t nc, ns;
+    pin_words(a0);
+    pin_words(b0);
+    bool more = next(c, s, nc, ns);
+    if (more) load(nc, ns, a1, b1);
+    compiler_fence();
+    body(c, s, nc, more, a0, b0);
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    s = ns;
+    pin_words(a1);
+    pin_words(b1);
+    more = next(c, s, nc, ns);
+    if (more) load(nc, ns, a0, b0);
+    compiler_fence();
+    body(c, s, nc, more, a1, b1);
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    s = ns;
+  }
+}
+
 // T = Y * B or Y^2 (Section 2 at block level; squares: pairs i <= j, the
 // cross pairs with a doubled operand, the diagonal blocks as Algorithm 2).
 // T rows: 2n normalised limbs and a zero top row.
@@ -329,51 +389,41 @@ __device__ __forceinline__ void scan_product(bool sqr, const LaneBuf& ws) {
   uint64_t cols[2 * H];
   sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
-  uint32_t a[H], b[H];
-  ld_rows<H>(ws, Lay::Y, a);
-  ld_rows<H>(ws, rb, b);
-  uint32_t c = 0, i = 0;
-#pragma nounroll
-  for (;;) {
-    const uint32_t j = c - i;
-    uint32_t nc = c, ni = i + 1;
+  // pair i of diagonal c: (i, c - i), up to the middle for squares
+  auto next = [&](uint32_t c, uint32_t i, uint32_t& nc, uint32_t& ni) {
+    nc = c;
+    ni = i + 1;
     if (ni > (c < K ? c : K - 1) || (sqr && ni > c - ni)) {
       nc = c + 1;
       ni = nc >= K ? nc - K + 1 : 0u;
     }
-    const bool more = nc < 2 * K - 1;
-    uint32_t na[H], nb[H];
-    if (more) {
-      ld_rows<H>(ws, Lay::Y + ni * H, na);
-      ld_rows<H>(ws, rb + (nc - ni) * H, nb);
-    }
-    compiler_fence();
-    if (sqr && i == j) {
+    return nc < 2 * K - 1;
+  };
+  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[H]) {
+    ld_rows<H>(ws, Lay::Y + i * H, x);
+    ld_rows<H>(ws, rb + (c - i) * H, y);
+  };
+  auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[H]) {
+    if (sqr && 2 * i == c) {
       uint32_t a2[H];
       sfor<0, H>([&](auto P) { a2[decltype(P)::value] = a[decltype(P)::value] << 1; });
-      blk_cols<H, 0, 2 * H - 2, true>(cols, a, a2);
+      blk_cols<H, 0, 2 * H - 2, true, RotMad>(cols, a, a2);
       sfor<0, H>([&](auto P) {
         constexpr int p = decltype(P)::value;
-        cols[2 * p] += (uint64_t)a[p] * a[p];
+        RotMad::template mac<p>(cols[2 * p], a[p], a[p]);
       });
     } else {
       if (sqr) sfor<0, H>([&](auto P) { b[decltype(P)::value] <<= 1; });
-      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+      blk_cols<H, 0, 2 * H - 2, false, RotMad>(cols, a, b);
     }
     if (nc != c) {  // diagonal c done: block c of T is final
       uint32_t o[H];
       blk_emit<H>(cols, carry, o);
       st_rows<H>(ws, Lay::T + c * H, o);
     }
-    compiler_fence();
-    if (!more) break;
-    c = nc;
-    i = ni;
-    sfor<0, H>([&](auto P) {
-      a[decltype(P)::value] = na[decltype(P)::value];
-      b[decltype(P)::value] = nb[decltype(P)::value];
-    });
-  }
+    (void)more;
+  };
+  run_pairs<H, H>(0u, 0u, next, load, body);
   uint32_t o[H];
   blk_emit<H>(cols, carry, o);
   st_rows<H>(ws, Lay::T + (2 * K - 1) * H, o);
@@ -388,42 +438,33 @@ __device__ __forceinline__ void scan_q(const LaneBuf& ws, const LaneBuf& cnp) {
   uint64_t cols[2 * H];
   sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
-  uint32_t a[H], b[H];
-  ld_rows<H>(ws, Lay::T, a);
-  ld_rows<H>(cnp, 0, b);
-  uint32_t c = 0, i = 0;
-#pragma nounroll
-  for (;;) {
-    uint32_t nc = c, ni = i + 1;
+  auto next = [&](uint32_t c, uint32_t i, uint32_t& nc, uint32_t& ni) {
+    nc = c;
+    ni = i + 1;
     if (ni > c) {
       nc = c + 1;
       ni = 0;
     }
-    const bool more = nc < K;
-    uint32_t na[H], nb[H];
-    if (more) {
-      ld_rows<H>(ws, Lay::T + ni * H, na);
-      ld_rows<H>(cnp, (nc - ni) * H, nb);
-    }
-    compiler_fence();
+    return nc < K;
+  };
+  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[H]) {
+    ld_rows<H>(ws, Lay::T + i * H, x);
+    ld_rows<H>(cnp, (c - i) * H, y);
+  };
+  auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[H]) {
     if (c + 1 < K)
-      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+      blk_cols<H, 0, 2 * H - 2, false, RotMad>(cols, a, b);
     else
-      blk_cols<H, 0, H - 1, false>(cols, a, b);
+      blk_cols<H, 0, H - 1, false, RotMad>(cols, a, b);
     if (nc != c) {
       uint32_t o[H];
       blk_emit<H>(cols, carry, o);  // the carry out of block K-1 is dropped: mod R
       st_rows<H>(ws, Lay::Q + c * H, o);
     }
-    compiler_fence();
-    if (!more) break;
-    c = nc;
-    i = ni;
-    sfor<0, H>([&](auto P) {
-      a[decltype(P)::value] = na[decltype(P)::value];
-      b[decltype(P)::value] = nb[decltype(P)::value];
-    });
-  }
+    (void)i;
+    (void)more;
+  };
+  run_pairs<H, H>(0u, 0u, next, load, body);
 }
 
 // Y = (T + q N) / R (Algorithm 6 step 4 / Algorithm 3).  TRUNC (Theorem 2):
@@ -445,31 +486,24 @@ __device__ __forceinline__ void scan_qn(const LaneBuf& ws, const LaneBuf& cn) {
     for (uint32_t i = 0; i + 2 <= K; ++i)
       cols[H - 2] += (uint64_t)ws.ld(Lay::Q + i * H + H - 1) * cn.ld((K - 2 - i) * H + H - 1);
   }
-  uint32_t a[H], b[H];
-  {
-    const uint32_t i0 = c0 >= K ? c0 - K + 1 : 0u;
-    ld_rows<H>(ws, Lay::Q + i0 * H, a);
-    ld_rows<H>(cn, (c0 - i0) * H, b);
-  }
-  uint32_t c = c0, i = c0 >= K ? c0 - K + 1 : 0u;
-#pragma nounroll
-  for (;;) {
-    uint32_t nc = c, ni = i + 1;
+  auto next = [&](uint32_t c, uint32_t i, uint32_t& nc, uint32_t& ni) {
+    nc = c;
+    ni = i + 1;
     if (ni > (c < K ? c : K - 1)) {
       nc = c + 1;
       ni = nc >= K ? nc - K + 1 : 0u;
     }
-    const bool more = nc < 2 * K - 1;
-    uint32_t na[H], nb[H];
-    if (more) {
-      ld_rows<H>(ws, Lay::Q + ni * H, na);
-      ld_rows<H>(cn, (nc - ni) * H, nb);
-    }
-    compiler_fence();
+    return nc < 2 * K - 1;
+  };
+  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[H]) {
+    ld_rows<H>(ws, Lay::Q + i * H, x);
+    ld_rows<H>(cn, (c - i) * H, y);
+  };
+  auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[H]) {
     if (TRUNC && c == K - 1)
-      blk_cols<H, H - 2, 2 * H - 2, false>(cols, a, b);
+      blk_cols<H, H - 2, 2 * H - 2, false, RotMad>(cols, a, b);
     else
-      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+      blk_cols<H, 0, 2 * H - 2, false, RotMad>(cols, a, b);
     if (nc != c) {  // diagonal c done: add block c of T, then emit or fold the carry
       uint32_t tb[H];
       ld_rows<H>(ws, Lay::T + c * H, tb);
@@ -491,15 +525,10 @@ __device__ __forceinline__ void scan_qn(const LaneBuf& ws, const LaneBuf& cn) {
         st_rows<H>(ws, Lay::Y + (c - K) * H, o);
       }
     }
-    compiler_fence();
-    if (!more) break;
-    c = nc;
-    i = ni;
-    sfor<0, H>([&](auto P) {
-      a[decltype(P)::value] = na[decltype(P)::value];
-      b[decltype(P)::value] = nb[decltype(P)::value];
-    });
-  }
+    (void)i;
+    (void)more;
+  };
+  run_pairs<H, H>(c0, c0 >= K ? c0 - K + 1 : 0u, next, load, body);
   // the top block: columns (2K-1) H .. 2n-1 and T's top limbs
   uint32_t tb[H];
   ld_rows<H>(ws, Lay::T + (2 * K - 1) * H, tb);
@@ -692,24 +721,53 @@ struct Res {
   static constexpr int NU = (2 * H - 2) / LP + 1;  // registers for the local columns 0 .. 2H - 2
 };
 
-// Br of the block at rows row0 .. row0 + H - 1 of b, for this lane's r
+// The lane's boundary entries of Br: the 2 (LP - 1) indices m < 0 and m > H - LP, whose row m + r can
+// fall outside the block.  Their reads take the clamped row qx and are cleared by keep after the read
+// has landed (a mask at read time would make the wavefront wait for it).
 template <int H, int LP>
-__device__ __forceinline__ void ld_shift(const LaneBuf& b, uint32_t row0, uint32_t r, uint32_t (&x)[Res<H, LP>::NB]) {
-  const uint32_t vr = b.vo + r * b.ls;
+struct ResLane {
+  static constexpr int NE = LP > 1 ? 2 * (LP - 1) : 1;
+  uint32_t qx[NE];
+  uint32_t keep[NE];
+  // entry e: m = e - (LP - 1) for e < LP - 1, else m = H - LP + 1 + (e - (LP - 1))
+  static constexpr int m_of(int e) { return e < LP - 1 ? e - (LP - 1) : H - LP + 1 + (e - (LP - 1)); }
+  __device__ __forceinline__ explicit ResLane(uint32_t r) {
+    sfor<0, (LP > 1 ? NE : 0)>([&](auto E) {
+      constexpr int e = decltype(E)::value;
+      const int q = m_of(e) + (int)r;
+      const bool in = q >= 0 && q <= H - 1;
+      qx[e] = (uint32_t)(in ? q : 0);
+      keep[e] = in ? 0xFFFFFFFFu : 0u;
+    });
+  }
+};
+
+// Br of the block at rows row0 .. row0 + H - 1 of b, for this lane's r, before res_mask
+template <int H, int LP, typename Buf>
+__device__ __forceinline__ void ld_shift(const Buf& b, uint32_t row0, uint32_t r, const ResLane<H, LP>& rl,
+                                         uint32_t (&x)[Res<H, LP>::NB]) {
   sfor<0, Res<H, LP>::NB>([&](auto I) {
     constexpr int m = (int)decltype(I)::value - (LP - 1);
     if constexpr (m >= 0 && m + LP - 1 <= H - 1) {
-      x[decltype(I)::value] = bload(b.r, vr, (row0 + (uint32_t)m) * b.ls);  // m + r < H for every r
+      x[decltype(I)::value] = b.ldx(row0 + (uint32_t)m, r);  // m + r < H for every r
     } else {
-      const int q = m + (int)r;
-      const bool in = q >= 0 && q <= H - 1;
-      const uint32_t v = bload(b.r, b.vo + (uint32_t)(in ? q : 0) * b.ls, row0 * b.ls);
-      x[decltype(I)::value] = in ? v : 0u;
+      constexpr int e = m < 0 ? m + (LP - 1) : (LP - 1) + (m - (H - LP + 1));
+      x[decltype(I)::value] = b.ldx(row0, rl.qx[e]);
     }
   });
 }
+template <int H, int LP>
+__device__ __forceinline__ void res_mask(const ResLane<H, LP>& rl, uint32_t (&x)[Res<H, LP>::NB]) {
+  sfor<0, (LP > 1 ? ResLane<H, LP>::NE : 0)>([&](auto E) {
+    constexpr int e = decltype(E)::value;
+    constexpr int m = ResLane<H, LP>::m_of(e);
+    x[m + LP - 1] &= rl.keep[e];
+  });
+}
 
-// cols[u] += sum over p of a[p] Br[LP u - p] for the registers ULO .. UHI, eight at a time
+
+// cols[u] += sum over p of a[p] Br[LP u - p] for the registers ULO .. UHI, eight at a time (the
+// products of one a[p] into eight accumulators, carry-outs rotated: RotMad)
 template <int H, int LP, int ULO, int UHI, int NU>
 __device__ __forceinline__ void res_cols(uint64_t (&cols)[NU], const uint32_t (&a)[H],
                                          const uint32_t (&bs)[Res<H, LP>::NB]) {
@@ -719,11 +777,17 @@ __device__ __forceinline__ void res_cols(uint64_t (&cols)[NU], const uint32_t (&
     constexpr int bk = (UHI + 1 - u0) < BK ? (UHI + 1 - u0) : BK;
     sfor<0, H>([&](auto P) {
       constexpr int p = decltype(P)::value;
-      sfor<0, bk>([&](auto D) {
-        constexpr int u = u0 + decltype(D)::value;
-        constexpr int m = LP * u - p;
-        if constexpr (m >= -(LP - 1) && m <= H - 1) cols[u] += (uint64_t)a[p] * bs[m + LP - 1];
-      });
+      constexpr auto ok = [](int u) { return LP * u - p >= -(LP - 1) && LP * u - p <= H - 1; };
+      constexpr auto ix = [](int u) { return LP * u - p + LP - 1; };
+      if constexpr (bk == 8 && ok(u0) && ok(u0 + 7)) {  // ok is an interval in u: its ends decide
+        RotMad::mad8(*reinterpret_cast<uint64_t(*)[8]>(&cols[u0]), bs[ix(u0)], bs[ix(u0 + 1)], bs[ix(u0 + 2)],
+                     bs[ix(u0 + 3)], bs[ix(u0 + 4)], bs[ix(u0 + 5)], bs[ix(u0 + 6)], bs[ix(u0 + 7)], a[p]);
+      } else {
+        sfor<0, bk>([&](auto D) {
+          constexpr int d = decltype(D)::value;
+          if constexpr (ok(u0 + d)) RotMad::template mac<d>(cols[u0 + d], bs[ix(u0 + d)], a[p]);
+        });
+      }
     });
   });
 }
@@ -778,83 +842,84 @@ __device__ __forceinline__ uint32_t diag_pairs(uint32_t c, bool sqr) {
   return top - ilo + 1;
 }
 
-template <int H, int K, int LP>
-__device__ __forceinline__ void scang_product(bool sqr, const LaneBuf& ws) {
+// With several lanes per instance, q takes the multiplier's rows (B is not read after the product), so
+// that Y, B and T (4n rows) are all a Montgomery operation needs of the lane's arrays.
+template <int H, int K>
+__device__ __forceinline__ constexpr uint32_t kQrows() { return BlkLayout<H, K>::B; }
+
+
+template <int H, int K, int LP, typename WB>
+__device__ __forceinline__ void scang_product(bool sqr, const WB& ws) {
   using Lay = BlkLayout<H, K>;
   constexpr int NB = Res<H, LP>::NB, NU = Res<H, LP>::NU;
   const uint32_t rb = sqr ? Lay::Y : Lay::B;
   const uint32_t r = threadIdx.x % LP;
+  const ResLane<H, LP> rl(r);
   uint64_t cols[NU];
   sfor<0, NU>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
-  auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[NB], uint32_t& sh) {
-    const uint32_t i = diag_ilo<K>(c) + s, j = c - i;
-    ld_rows<H>(ws, Lay::Y + i * H, x);
-    ld_shift<H, LP>(ws, rb + j * H, r, y);
-    sh = sqr && i < j ? 1u : 0u;  // cross pairs of a square count twice
-  };
-  uint32_t a[H], b[NB], sh;
-  load(0, 0, a, b, sh);
-  uint32_t c = 0, s = 0;
-#pragma nounroll
-  for (;;) {
-    uint32_t nc = c, ns = s + 1;
+  // pair s of diagonal c: (i, c - i), i = diag_ilo(c) + s
+  auto next = [&](uint32_t c, uint32_t s, uint32_t& nc, uint32_t& ns) {
+    nc = c;
+    ns = s + 1;
     if (ns >= diag_pairs<K>(c, sqr)) {
       nc = c + 1;
       ns = 0;
     }
-    const bool more = nc < 2 * K - 1;
-    uint32_t na[H], nb[NB], nsh = 0;
-    if (more) load(nc, ns, na, nb, nsh);
-    compiler_fence();
-    sfor<0, NB>([&](auto P) { b[decltype(P)::value] <<= sh; });
+    return nc < 2 * K - 1;
+  };
+  auto load = [&](uint32_t c, uint32_t s, uint32_t (&x)[H], uint32_t (&y)[NB]) {
+    const uint32_t i = diag_ilo<K>(c) + s, j = c - i;
+    ld_rows<H>(ws, Lay::Y + i * H, x);
+    ld_shift<H, LP>(ws, rb + j * H, r, rl, y);
+  };
+  auto body = [&](uint32_t c, uint32_t s, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[NB]) {
+    const uint32_t i = diag_ilo<K>(c) + s;
+    const uint32_t sh = sqr && 2 * i < c ? 1u : 0u;  // cross pairs of a square count twice
+    res_mask<H, LP>(rl, b);
+    sfor<0, H>([&](auto P) { a[decltype(P)::value] <<= sh; });
     res_cols<H, LP, 0, NU - 1>(cols, a, b);
     if (nc != c) {  // diagonal c done: block c of T is final
       uint32_t o[H];
       res_emit<H, LP>(cols, carry, o);
       st_rows<H>(ws, Lay::T + c * H, o);
-      res_roll<H, LP>(cols, r);
+      if (more) res_roll<H, LP>(cols, r);
     }
-    compiler_fence();
-    if (!more) break;
-    c = nc;
-    s = ns;
-    sh = nsh;
-    sfor<0, H>([&](auto P) { a[decltype(P)::value] = na[decltype(P)::value]; });
-    sfor<0, NB>([&](auto P) { b[decltype(P)::value] = nb[decltype(P)::value]; });
-  }
+    (void)more;
+  };
+  run_pairs<H, NB>(0u, 0u, next, load, body);
+  // the top block: the last diagonal's high columns
+  res_roll<H, LP>(cols, r);
   uint32_t o[H];
-  res_emit<H, LP>(cols, carry, o);
+  res_emit<H, LP>(cols, carry, o);  // no carry remains: T < 2^(28 2n); T's top row is not kept here
   st_rows<H>(ws, Lay::T + (2 * K - 1) * H, o);
-  ws.st(Lay::T + 2 * Lay::n, (uint32_t)carry);
 }
 
-template <int H, int K, int LP>
-__device__ __forceinline__ void scang_q(const LaneBuf& ws, const LaneBuf& cnp) {
+template <int H, int K, int LP, typename WB>
+__device__ __forceinline__ void scang_q(const WB& ws, const LaneBuf& cnp) {
   using Lay = BlkLayout<H, K>;
   constexpr int NB = Res<H, LP>::NB, NU = Res<H, LP>::NU;
   const uint32_t r = threadIdx.x % LP;
+  const ResLane<H, LP> rl(r);
   uint64_t cols[NU];
   sfor<0, NU>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
-  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[NB]) {
-    ld_rows<H>(ws, Lay::T + i * H, x);
-    ld_shift<H, LP>(cnp, (c - i) * H, r, y);
-  };
-  uint32_t a[H], b[NB];
-  load(0, 0, a, b);
-  uint32_t c = 0, i = 0;
-#pragma nounroll
-  for (;;) {
-    uint32_t nc = c, ni = i + 1;
+  // pair i of diagonal c < K: (i, c - i)
+  auto next = [&](uint32_t c, uint32_t i, uint32_t& nc, uint32_t& ni) {
+    nc = c;
+    ni = i + 1;
     if (ni > c) {
       nc = c + 1;
       ni = 0;
     }
-    const bool more = nc < K;
-    uint32_t na[H], nb[NB];
-    if (more) load(nc, ni, na, nb);
-    compiler_fence();
+    return nc < K;
+  };
+  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[NB]) {
+    ld_rows<H>(ws, Lay::T + i * H, x);
+    ld_shift<H, LP>(cnp, (c - i) * H, r, rl, y);
+  };
+  auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[NB]) {
+    res_mask<H, LP>(rl, b);
     if (c + 1 < K)
       res_cols<H, LP, 0, NU - 1>(cols, a, b);
     else  // the anti-diagonal: its low H columns (a few more in some lanes, never read)
@@ -862,37 +927,35 @@ __device__ __forceinline__ void scang_q(const LaneBuf& ws, const LaneBuf& cnp) {
     if (nc != c) {
       uint32_t o[H];
       res_emit<H, LP>(cols, carry, o);  // the carry out of block K-1 is dropped: mod R
-      st_rows<H>(ws, Lay::Q + c * H, o);
+      st_rows<H>(ws, kQrows<H, K>() + c * H, o);
       if (more) res_roll<H, LP>(cols, r);
     }
-    compiler_fence();
-    if (!more) break;
-    c = nc;
-    i = ni;
-    sfor<0, H>([&](auto P) { a[decltype(P)::value] = na[decltype(P)::value]; });
-    sfor<0, NB>([&](auto P) { b[decltype(P)::value] = nb[decltype(P)::value]; });
-  }
+    (void)i;
+  };
+  run_pairs<H, NB>(0u, 0u, next, load, body);
 }
 
 // cols += block c of T, each lane its own columns k = LP u + r < H
-template <int H, int LP, int NU>
-__device__ __forceinline__ void res_add_rows(uint64_t (&cols)[NU], const LaneBuf& ws, uint32_t row0, uint32_t r) {
-  const uint32_t vr = ws.vo + r * ws.ls;
+template <int H, int LP, int NU, typename WB>
+__device__ __forceinline__ void res_add_rows(uint64_t (&cols)[NU], const WB& ws, uint32_t row0, uint32_t r) {
   sfor<0, (H - 1) / LP + 1>([&](auto U) {
     constexpr int u = decltype(U)::value;
-    const uint32_t t = bload(ws.r, vr, (row0 + (uint32_t)(LP * u)) * ws.ls);
-    if constexpr (LP * u + LP - 1 <= H - 1)
-      cols[u] += t;
-    else
-      cols[u] += (uint32_t)(LP * u) + r <= (uint32_t)(H - 1) ? t : 0u;
+    if constexpr (LP * u + LP - 1 <= H - 1) {
+      cols[u] += ws.ldx(row0 + (uint32_t)(LP * u), r);
+    } else {  // the lanes past the block read its row LP u (inside it) and add nothing
+      const bool in = (uint32_t)(LP * u) + r <= (uint32_t)(H - 1);
+      const uint32_t t = ws.ldx(row0 + (uint32_t)(LP * u), in ? r : 0u);
+      cols[u] += in ? t : 0u;
+    }
   });
 }
 
-template <int H, int K, bool TRUNC, int LP>
-__device__ __forceinline__ void scang_qn(const LaneBuf& ws, const LaneBuf& cn) {
+template <int H, int K, bool TRUNC, int LP, typename WB>
+__device__ __forceinline__ void scang_qn(const WB& ws, const LaneBuf& cn) {
   using Lay = BlkLayout<H, K>;
   constexpr int NB = Res<H, LP>::NB, NU = Res<H, LP>::NU;
   const uint32_t r = threadIdx.x % LP;
+  const ResLane<H, LP> rl(r);
   uint64_t cols[NU];
   sfor<0, NU>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
@@ -904,26 +967,24 @@ __device__ __forceinline__ void scang_qn(const LaneBuf& ws, const LaneBuf& cn) {
     const uint32_t own = r == (uint32_t)((H - 2) % LP) ? 0xFFFFFFFFu : 0u;
 #pragma nounroll
     for (uint32_t i = 0; i + 2 <= K; ++i)
-      cols[(H - 2) / LP] += (uint64_t)(ws.ld(Lay::Q + i * H + H - 1) & own) * cn.ld((K - 2 - i) * H + H - 1);
+      cols[(H - 2) / LP] += (uint64_t)(ws.ld(kQrows<H, K>() + i * H + H - 1) & own) * cn.ld((K - 2 - i) * H + H - 1);
   }
-  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[NB]) {
-    ld_rows<H>(ws, Lay::Q + i * H, x);
-    ld_shift<H, LP>(cn, (c - i) * H, r, y);
-  };
-  uint32_t a[H], b[NB];
-  uint32_t c = c0, i = diag_ilo<K>(c0);
-  load(c, i, a, b);
-#pragma nounroll
-  for (;;) {
-    uint32_t nc = c, ni = i + 1;
+  // pair i of diagonal c: (i, c - i), diag_ilo(c) <= i <= min(c, K - 1)
+  auto next = [&](uint32_t c, uint32_t i, uint32_t& nc, uint32_t& ni) {
+    nc = c;
+    ni = i + 1;
     if (ni > (c < K ? c : K - 1)) {
       nc = c + 1;
       ni = diag_ilo<K>(nc);
     }
-    const bool more = nc < 2 * K - 1;
-    uint32_t na[H], nb[NB];
-    if (more) load(nc, ni, na, nb);
-    compiler_fence();
+    return nc < 2 * K - 1;
+  };
+  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[NB]) {
+    ld_rows<H>(ws, kQrows<H, K>() + i * H, x);
+    ld_shift<H, LP>(cn, (c - i) * H, r, rl, y);
+  };
+  auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[NB]) {
+    res_mask<H, LP>(rl, b);
     if (TRUNC && c == K - 1)  // columns >= H-2 (a few lower ones in some lanes, never read)
       res_cols<H, LP, (H - 1 - LP) / LP, NU - 1>(cols, a, b);
     else
@@ -941,13 +1002,10 @@ __device__ __forceinline__ void scang_qn(const LaneBuf& ws, const LaneBuf& cn) {
       }
       res_roll<H, LP>(cols, r);
     }
-    compiler_fence();
-    if (!more) break;
-    c = nc;
-    i = ni;
-    sfor<0, H>([&](auto P) { a[decltype(P)::value] = na[decltype(P)::value]; });
-    sfor<0, NB>([&](auto P) { b[decltype(P)::value] = nb[decltype(P)::value]; });
-  }
+    (void)i;
+    (void)more;
+  };
+  run_pairs<H, NB>(c0, diag_ilo<K>(c0), next, load, body);
   // the top block: columns (2K-1) H .. 2n-1 and T's top limbs
   res_add_rows<H, LP>(cols, ws, Lay::T + (2 * K - 1) * H, r);
   uint32_t o[H];
@@ -959,8 +1017,8 @@ __device__ __forceinline__ void scang_qn(const LaneBuf& ws, const LaneBuf& cn) {
 // n = K H; context blocks come from the limb-major context arrays.  LP lanes
 // per instance (1, or 2 or 4 for the schoolbook product).
 // KREDC: the truncated q N by one-level Karatsuba (scan_qn_kara; one lane per instance, K even).
-template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false>
-__device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const LaneBuf& cn, const LaneBuf& cnp) {
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false, typename WB>
+__device__ __forceinline__ void mont_blk(bool sqr, const WB& ws, const LaneBuf& cn, const LaneBuf& cnp) {
   static_assert(LP == 1 || ((LP == 2 || LP == 4) && !KARA), "several lanes per instance: schoolbook products only");
   static_assert(!KREDC || (LP == 1 && TRUNC && K % 2 == 0), "Karatsuba-truncated q N: one lane, even block count");
   if constexpr (LP > 1) {
@@ -984,8 +1042,8 @@ __device__ __forceinline__ void mont_blk(bool sqr, const LaneBuf& ws, const Lane
 }
 
 // Loads the RW-word little-endian value at src into rows row .. row+n-1 (28-bit limbs).
-template <int H, int K>
-__device__ __forceinline__ void expand_rows(const LaneBuf& ws, uint32_t row, const uint64_t* __restrict__ src,
+template <int H, int K, typename Buf>
+__device__ __forceinline__ void expand_rows(const Buf& ws, uint32_t row, const uint64_t* __restrict__ src,
                                             uint32_t words) {
   constexpr uint32_t n = H * K;
 #pragma nounroll
@@ -997,8 +1055,8 @@ __device__ __forceinline__ void expand_rows(const LaneBuf& ws, uint32_t row, con
   }
 }
 
-template <int H, int K>
-__device__ __forceinline__ void contract_rows(const LaneBuf& ws, uint32_t row, uint64_t* __restrict__ dst,
+template <int H, int K, typename Buf>
+__device__ __forceinline__ void contract_rows(const Buf& ws, uint32_t row, uint64_t* __restrict__ dst,
                                               uint32_t words) {
   constexpr uint32_t n = H * K;
 #pragma nounroll
@@ -1045,13 +1103,52 @@ __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __r
 // ---- modexp, block version (same schedule as k_modexp) ----------------------
 // A tile is 64 / LP instances (LP lanes per instance).  tws: this
 // wavefront's own workspace region (BlkLayout rows(w) rows of 64 / LP
-// instances, 256 / LP bytes per row), contiguous in memory.
-template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false>
+// instances, 256 / LP bytes per row), contiguous in memory.  hot: where the
+// Montgomery operations keep Y, B (q) and T -- the same region (LDSHOT
+// false) or 4n rows of LDS for the tile (LDSHOT, several lanes per instance,
+// s_hot 4n (64 / LP) words); the window table stays in the region.
+// With LDSHOT the lanes of a group split the table scan and the table's
+// copies by residue (limb LP t + r in lane r): each lane reads back from the
+// table only the limbs it wrote there, and the rows it writes to the LDS
+// arrays are read by the whole group after a compiler fence (LDS operations of
+// one wavefront are performed in order).  In the workspace path every lane
+// copies and scans every limb, so no lane reads what another lane wrote.
+
+// dst rows [dr, dr + n) = src rows [sr, sr + n), lane r of each group of LP copying the limbs LP t + r
+template <int LP, int NL, typename DB, typename SB>
+__device__ __forceinline__ void copy_rows_split(const DB& d, uint32_t dr, const SB& sb, uint32_t sr, uint32_t r) {
+  if constexpr (LP == 1) {
+    copy_rows<37>(d, dr, sb, sr, NL);
+  } else {
+    constexpr int NT = (NL + LP - 1) / LP;
+    uint32_t x[NT];
+    sfor<0, NT>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      if constexpr (LP * t + LP <= NL) {
+        x[t] = sb.ldx(sr + (uint32_t)(LP * t), r);
+      } else {  // the last t of some lanes is past the array
+        const bool in = LP * t + (int)r < NL;
+        x[t] = sb.ldx(sr + (uint32_t)(LP * t), in ? r : 0u);
+      }
+    });
+    sfor<0, NT>([&](auto T) {
+      constexpr int t = decltype(T)::value;
+      if constexpr (LP * t + LP <= NL)
+        d.stx(dr + (uint32_t)(LP * t), r, x[t]);
+      else if (LP * t + (int)r < NL)
+        d.stx(dr + (uint32_t)(LP * t), r, x[t]);
+    });
+  }
+}
+
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false, bool LDSHOT = false>
 __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
                                                 const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                 uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
                                                 uint64_t* __restrict__ out, uint32_t count, uint32_t* tws,
-                                                uint32_t tws_bytes, uint32_t coff, uint32_t tile0) {
+                                                uint32_t tws_bytes, uint32_t coff, uint32_t tile0,
+                                                uint32_t* s_hot = nullptr) {
+  static_assert(!LDSHOT || LP > 1, "LDS-resident arrays: several lanes per instance");
   using Lay = BlkLayout<H, K>;
   constexpr uint32_t n = Lay::n;
   const uint32_t slot = (threadIdx.x & 63u) / LP;  // this lane's instance within the tile
@@ -1062,6 +1159,15 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
   uint32_t c = cidx ? cidx[inst] : inst + coff;
   c = c < ctx.count ? c : 0u;
   const LaneBuf ws{make_buf(tws, tws_bytes), slot * 4u, 256u / LP};
+  const uint32_t r = threadIdx.x % LP;
+  constexpr int SP = LDSHOT ? LP : 1;  // lanes that split the table's scan and copies
+  const uint32_t rs = LDSHOT ? r : 0u;
+  using HotBuf = typename std::conditional<LDSHOT, LdsBuf, LaneBuf>::type;
+  HotBuf hot;
+  if constexpr (LDSHOT)
+    hot = LdsBuf{s_hot + slot, 64u / LP};
+  else
+    hot = ws;
   const uint32_t cbytes = n * ctx.stride * 4u;
   const LaneBuf cn{make_buf(ctx.n, cbytes), c * 4u, ctx.stride * 4u};
   const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
@@ -1072,8 +1178,8 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
   const uint32_t nent = 1u << w;
   const uint32_t nwin = ebits ? (ebits + w - 1) / w : 1u;
   // G[0] = R mod N
-  copy_rows<H>(ws, Lay::G, cr1, 0, n);
-  expand_rows<H, K>(ws, Lay::Y, base + (size_t)inst * bw, bw);
+  copy_rows_split<SP, n>(ws, Lay::G, cr1, 0, rs);
+  expand_rows<H, K>(hot, Lay::Y, base + (size_t)inst * bw, bw);
 
   const uint32_t n_tab = nent - 1;
   const uint32_t n_main = (nwin - 1) * (w + 1);
@@ -1090,9 +1196,9 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
       kind = kLoadSel;
       win = nwin - 1;
     } else if (s < n_tab + 1 + n_main) {
-      const uint32_t r = s - n_tab - 1;
-      win = nwin - 2 - r / (w + 1);
-      kind = (r % (w + 1)) < w ? kSqr : kMulSel;
+      const uint32_t step = s - n_tab - 1;
+      win = nwin - 2 - step / (w + 1);
+      kind = (step % (w + 1)) < w ? kSqr : kMulSel;
     } else {
       kind = kMulOne;
     }
@@ -1107,42 +1213,66 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
       // full masked scan of the table, H limbs at a time, SE entries per
       // iteration (SE H reads in flight; the registers of the Montgomery
       // operation are free here).  With fewer than SE entries (w < 3) the
-      // missing ones re-read entry 0 under a zero mask.
+      // missing ones re-read entry 0 under a zero mask.  Lane rs of a group
+      // of SP scans the limbs SP t + rs (t in chunks of H).
       constexpr uint32_t SE = 8;
+      constexpr uint32_t NT = (n + SP - 1) / SP;        // limbs per lane
+      constexpr uint32_t CH = NT < H ? NT : H;          // limbs per lane and chunk
+      constexpr bool kFull = n % SP == 0 && NT % CH == 0;  // every (chunk, i, lane) names a limb
 #pragma nounroll
-      for (uint32_t blk = 0; blk < K; ++blk) {
-        uint32_t acc[H];
-        sfor<0, H>([&](auto I) { acc[decltype(I)::value] = 0; });
+      for (uint32_t t0 = 0; t0 < NT; t0 += CH) {
+        uint32_t acc[CH];
+        sfor<0, CH>([&](auto I) { acc[decltype(I)::value] = 0; });
 #pragma nounroll
         for (uint32_t e = 0; e < nent; e += SE) {
-          uint32_t g[SE][H];
+          uint32_t g[SE][CH];
           uint32_t mask[SE];
           sfor<0, SE>([&](auto U) {
             constexpr uint32_t u = decltype(U)::value;
             const bool in = e + u < nent;
             mask[u] = in && e + u == bits ? 0xFFFFFFFFu : 0u;
-            ld_rows<H>(ws, Lay::G + (in ? e + u : 0u) * n + blk * H, g[u]);
+            const uint32_t er = Lay::G + (in ? e + u : 0u) * n;
+            sfor<0, CH>([&](auto I) {
+              constexpr uint32_t i = decltype(I)::value;
+              const uint32_t l = SP * (t0 + i) + rs;  // this lane's limb
+              if constexpr (kFull) {
+                g[u][i] = ws.ldx(er, l);
+              } else {  // past n: row n - 1 under a zero mask
+                const bool li = l < n;
+                g[u][i] = ws.ldx(er, li ? l : n - 1u) & (li ? 0xFFFFFFFFu : 0u);
+              }
+            });
           });
-          sfor<0, H>([&](auto I) {
+          sfor<0, CH>([&](auto I) {
             constexpr int i = decltype(I)::value;
             uint32_t v = acc[i];
             sfor<0, SE>([&](auto U) { v |= g[decltype(U)::value][i] & mask[decltype(U)::value]; });
             acc[i] = v;
           });
         }
-        st_rows<H>(ws, dst + blk * H, acc);
+        sfor<0, CH>([&](auto I) {
+          constexpr uint32_t i = decltype(I)::value;
+          const uint32_t l = SP * (t0 + i) + rs;
+          if constexpr (kFull)
+            hot.stx(dst, l, acc[i]);
+          else if (l < n)
+            hot.stx(dst, l, acc[i]);
+        });
       }
+      compiler_fence();
       if (kind == kLoadSel) continue;
     } else if (kind == kMulR2) {
-      copy_rows<H>(ws, Lay::B, cr2, 0, n);
+      copy_rows_split<SP, n>(hot, Lay::B, cr2, 0, rs);
     } else if (kind == kMulG1) {
-      copy_rows<H>(ws, Lay::B, ws, Lay::G + n, n);
+      copy_rows_split<SP, n>(hot, Lay::B, ws, Lay::G + n, rs);
     } else if (kind == kMulOne) {
 #pragma nounroll
-      for (uint32_t i = 0; i < n; ++i) ws.st(Lay::B + i, i == 0 ? 1u : 0u);
+      for (uint32_t i = 0; i < n; ++i) hot.st(Lay::B + i, i == 0 ? 1u : 0u);
     }
-    mont_blk<H, K, TRUNC, KARA, LP, KREDC>(kind == kSqr, ws, cn, cnp);
-    if (store_e >= 0) copy_rows<H>(ws, Lay::G + (uint32_t)store_e * n, ws, Lay::Y, n);
+    compiler_fence();
+    mont_blk<H, K, TRUNC, KARA, LP, KREDC>(kind == kSqr, hot, cn, cnp);
+    compiler_fence();
+    if (store_e >= 0) copy_rows_split<SP, n>(ws, Lay::G + (uint32_t)store_e * n, hot, Lay::Y, rs);
   }
   // canonical result: subtract N once if Y >= N, in constant time: B = Y - N, then every limb of B
   // becomes Y's or stays B's under an all-ones / all-zero mask, so the rows read and written, and
@@ -1150,15 +1280,15 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
   int64_t br = 0;
 #pragma nounroll
   for (uint32_t i = 0; i < n; ++i) {
-    const int64_t v = (int64_t)ws.ld(Lay::Y + i) - (int64_t)cn.ld(i) + br;
-    ws.st(Lay::B + i, (uint32_t)v & kLimbMask);
+    const int64_t v = (int64_t)hot.ld(Lay::Y + i) - (int64_t)cn.ld(i) + br;
+    hot.st(Lay::B + i, (uint32_t)v & kLimbMask);
     br = v >> kLimbBits;
   }
   const uint32_t keep_y = (uint32_t)br;  // br is -1 (Y < N: keep Y) or 0 (keep Y - N)
 #pragma nounroll
   for (uint32_t i = 0; i < n; ++i)
-    ws.st(Lay::B + i, (ws.ld(Lay::Y + i) & keep_y) | (ws.ld(Lay::B + i) & ~keep_y));
-  if (writer) contract_rows<H, K>(ws, Lay::B, out + (size_t)inst * bw, bw);
+    hot.st(Lay::B + i, (hot.ld(Lay::Y + i) & keep_y) | (hot.ld(Lay::B + i) & ~keep_y));
+  if (writer) contract_rows<H, K>(hot, Lay::B, out + (size_t)inst * bw, bw);
 }
 
 template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false>
@@ -1171,8 +1301,11 @@ __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* _
   const uint32_t tbytes = BlkLayout<H, K>::rows(w) * (256u / LP);  // this block's region
   if ((uint64_t)(blockIdx.x + 1) * tbytes > ws_bytes) return;  // unreachable: the launcher checked ws
   stagger<H * K>(blockIdx.x, w);
-  modexp_tile_blk<H, K, TRUNC, KARA, LP, KREDC>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
-                                                ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff, tile0);
+  constexpr bool kLds = LP == 4;  // 4n rows of 16 words: 37.9 KB at 4096 bits, four wavefronts per CU
+  __shared__ uint32_t s_hot[kLds ? 4 * H * K * (64 / LP) : 1];
+  modexp_tile_blk<H, K, TRUNC, KARA, LP, KREDC, kLds>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
+                                                      ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff,
+                                                      tile0, s_hot);
 }
 
 }  // namespace mx

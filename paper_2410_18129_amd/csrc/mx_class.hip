@@ -262,11 +262,12 @@ hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx
     }
   }
   if constexpr (kBlock || kHasBlk) {
-    if (kBlock || impl == 1 || impl == 3 || impl == 4) {
+    if (kBlock || impl == 1 || impl == 3 || impl == 4 || impl == 5) {
       // a batch that leaves SIMDs without a wavefront runs four or two lanes per
       // instance (lower latency, more lanes) unless one lane (impl 3) or at most two
-      // (impl 4) were asked for; the workspace has room for any of them
-      if (count <= kFourLaneMax && impl != 3 && impl != 4) {
+      // (impl 4) were asked for; four at any size when asked for (impl 5); the
+      // workspace has room for any of them
+      if ((count <= kFourLaneMax && impl != 3 && impl != 4) || impl == 5) {
         const uint32_t blocks4 = (count + 15) / 16;
         if (trunc)
           hipLaunchKernelGGL((k_modexp_blk<kH, kK, true, false, 4>), dim3(blocks4), dim3(64), 0, st, ctx, cidx, base,

@@ -57,6 +57,7 @@ __global__ void k_reset_counter(uint32_t* counter) {
 
 __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
   __shared__ uint32_t s_ctx[2 * 74 * 64];  // N, N' staging of the largest register-resident class
+  static_assert(2 * 74 * 64 >= 4 * 37 * 4 * 16, "a 4096-bit four-lane tile's Y, B and T rows fit s_ctx");
   const uint32_t lane = threadIdx.x & 63u;
   // the first tiles of all waves start together and are the costliest (the
   // largest class): spread their start phases as a 4096-bit, window-5 launch does
@@ -89,7 +90,10 @@ __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
                                      mb.count, tw, tb, 0u, tile0);
         break;
       case kF3072B:
-        if (mb.lanes == 2)
+        if (mb.lanes == 4)  // the tile's arrays in the LDS that register-resident tiles stage N, N' in
+          modexp_tile_blk<37, 3, true, false, 4, false, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords,
+                                                              mb.w, 48u, mb.out, mb.count, tw, tb, 0u, tile0, s_ctx);
+        else if (mb.lanes == 2)
           modexp_tile_blk<37, 3, true, false, 2>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 48u,
                                                  mb.out, mb.count, tw, tb, 0u, tile0);
         else
@@ -105,7 +109,10 @@ __global__ void __launch_bounds__(64) k_modexp_mixed(MixedArgs args) {
                                            mb.count, tw, tb, 0u, tile0);
         break;
       default:  // 4096 bits, schoolbook
-        if (mb.lanes == 2)
+        if (mb.lanes == 4)
+          modexp_tile_blk<37, 4, true, false, 4, false, true>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords,
+                                                              mb.w, 64u, mb.out, mb.count, tw, tb, 0u, tile0, s_ctx);
+        else if (mb.lanes == 2)
           modexp_tile_blk<37, 4, true, false, 2>(mb.ctx, mb.cidx, mb.base, mb.ex, mb.ebits, mb.ewords, mb.w, 64u,
                                                  mb.out, mb.count, tw, tb, 0u, tile0);
         else
@@ -135,12 +142,13 @@ __global__ void k_fill(uint64_t* p, uint32_t rows, uint32_t words, uint32_t topb
 
 namespace {
 
-// Lanes per instance of a batch: MX_ONE_LANE or MX_TWO_LANES where the family has both (the block
-// schoolbook kernels of 3072 and 4096 bits), else the default: two for 4096-bit schoolbook tiles (the
-// longest, which otherwise bound the launch), one for the rest.  0 if the flags ask for what the
-// family does not have.
+// Lanes per instance of a batch: MX_ONE_LANE, MX_TWO_LANES or MX_FOUR_LANES where the family has
+// them (the block schoolbook kernels of 3072 and 4096 bits), else the default: two for 4096-bit
+// schoolbook tiles (the longest, which otherwise bound the launch), one for the rest.  0 if the flags
+// ask for what the family does not have.
 uint32_t lanes_of(uint32_t fam, uint32_t flags) {
   const bool two_ok = fam == mx::kF3072B || fam == mx::kF4096B;
+  if (flags & MX_FOUR_LANES) return two_ok ? 4u : 0u;
   if (flags & MX_TWO_LANES) return two_ok ? 2u : 0u;
   if (flags & MX_ONE_LANE) return 1u;
   return fam == mx::kF4096B ? 2u : 1u;
@@ -195,15 +203,16 @@ mx_status mx_mixed_plan_create(mx_mixed_plan** out, const mx_batch_desc* batches
     const mx_batch_desc& d = batches[b];
     if (!d.ctx) return mx_fail(MX_EINVAL, "batch %u: ctx is NULL", b);
     if (d.ctx->device != dev) return mx_fail(MX_EINVAL, "batch %u: context lives on another device", b);
-    if (d.flags & ~(uint32_t)(MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_TWO_LANES))
+    if (d.flags & ~(uint32_t)(MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE | MX_TWO_LANES | MX_FOUR_LANES))
       return mx_fail(MX_EUNSUPPORTED, "batch %u: the mixed launch runs the truncated reduction only", b);
-    if ((d.flags & MX_ONE_LANE) && (d.flags & MX_TWO_LANES))
-      return mx_fail(MX_EINVAL, "batch %u: MX_ONE_LANE and MX_TWO_LANES exclude each other", b);
+    const uint32_t lf = d.flags & (uint32_t)(MX_ONE_LANE | MX_TWO_LANES | MX_FOUR_LANES);
+    if (lf & (lf - 1))
+      return mx_fail(MX_EINVAL, "batch %u: MX_ONE_LANE, MX_TWO_LANES and MX_FOUR_LANES exclude each other", b);
     if (!family_of(d.ctx, d.flags, &fam[b]))
       return mx_fail(MX_EUNSUPPORTED, "batch %u: %u-bit class not in the mixed launch", b, d.ctx->bits);
     if (lanes_of(fam[b], d.flags) == 0)
-      return mx_fail(MX_EUNSUPPORTED, "batch %u: two lanes per instance exist for the 3072- and 4096-bit "
-                     "schoolbook tiles only", b);
+      return mx_fail(MX_EUNSUPPORTED, "batch %u: two or four lanes per instance exist for the 3072- and "
+                     "4096-bit schoolbook tiles only", b);
     if (d.n && (!d.base || !d.out || (d.exp_bits && !d.exp))) return mx_fail(MX_EINVAL, "batch %u: NULL pointer", b);
     if (!d.ctx_idx && d.n > d.ctx->count) return mx_fail(MX_EINVAL, "batch %u: n exceeds the context count", b);
     if (d.window > 8) return mx_fail(MX_EINVAL, "batch %u: window outside 1..8", b);

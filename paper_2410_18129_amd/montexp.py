@@ -20,6 +20,7 @@ MX_REDC_TRUNC, MX_REDC_PLAIN, MX_IMPL_BLOCK, MX_MUL_KARATSUBA, MX_ONE_LANE, MX_R
 MX_REDC_KARATSUBA = 64
 MX_MUL_KARATSUBA2 = 128
 MX_CHECK_INPUTS = 256
+MX_FOUR_LANES = 512
 SIZE_CLASSES = (64, 128, 256, 512, 1024, 2048, 3072, 4096)
 LIMB_BITS = 28
 
@@ -261,11 +262,12 @@ def mont_sqr(ctx, a, out=None, ctx_idx=None, plain=False, stream=None, block=Fal
 
 
 def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=False, stream=None, block=False,
-           one_lane=False, cios=False, two_lanes=False, kara_redc=False, check_inputs=False):
+           one_lane=False, cios=False, two_lanes=False, kara_redc=False, check_inputs=False, four_lanes=False):
     """base^exp mod N per instance; base: int64 [n, words], exp: int64 [n, ceil(exp_bits/64)].
 
     one_lane: block kernels keep one lane per instance for small batches too (MX_ONE_LANE);
-    two_lanes: at most two lanes per instance (MX_TWO_LANES).
+    two_lanes: at most two lanes per instance (MX_TWO_LANES);
+    four_lanes: four lanes per instance at any batch size (MX_FOUR_LANES; block schoolbook kernels).
     cios: word-interleaved Montgomery products (Algorithm 4, MX_REDC_CIOS; classes up to 2048 bits).
     kara_redc: truncated high half of q N by one-level Karatsuba (MX_REDC_KARATSUBA; the register-resident
     classes, and the block kernels at 2048 and 4096 bits with one lane per instance).
@@ -281,7 +283,7 @@ def modexp(ctx, base, exp, exp_bits, window=0, out=None, ctx_idx=None, plain=Fal
     _check_idx(ctx_idx, n, ctx)
     flags = (_redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0) |
              (MX_TWO_LANES if two_lanes else 0) | (MX_REDC_KARATSUBA if kara_redc else 0) |
-             (MX_CHECK_INPUTS if check_inputs else 0))
+             (MX_CHECK_INPUTS if check_inputs else 0) | (MX_FOUR_LANES if four_lanes else 0))
     if n:  # one launch's workspace (0, a no-op, for arguments the call itself rejects)
         ctx.reserve(modexp_ws_bytes(ctx, n, window, flags=flags))
     _check(lib().modexp_batch(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None, exp_bits,
@@ -294,7 +296,7 @@ class MixedPlan:
 
     batches: list of dicts with keys ctx, base, exp, exp_bits, out and
     optionally window, block (bool), karatsuba (bool), flags (MX_IMPL_BLOCK,
-    MX_MUL_KARATSUBA, MX_ONE_LANE, MX_TWO_LANES), ctx_idx, tile_cost.  The device buffers
+    MX_MUL_KARATSUBA, MX_ONE_LANE, MX_TWO_LANES, MX_FOUR_LANES), ctx_idx, tile_cost.  The device buffers
     are captured by the plan; every launch reads and writes them.
     """
 
@@ -354,14 +356,14 @@ def modexp_ws_bytes(ctx, n, window=0, block=False, flags=None):
     nb = ctypes.c_size_t()
     f = _impl_flags(block) if flags is None else flags
     st = lib().modexp_ws_bytes(ctx.handle, n, window, f & (MX_IMPL_BLOCK | MX_MUL_KARATSUBA | MX_ONE_LANE |
-                                                          MX_TWO_LANES), ctypes.byref(nb))
+                                                          MX_TWO_LANES | MX_FOUR_LANES), ctypes.byref(nb))
     if st != MX_OK:  # the batch call reports the same error with its own name
         return 0
     return nb.value
 
 
 def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, plain=False, stream=None,
-              block=False, n=None, one_lane=False, cios=False, two_lanes=False):
+              block=False, n=None, one_lane=False, cios=False, two_lanes=False, four_lanes=False):
     """modexp with a caller-owned workspace tensor (uint8/any dtype, device); n rows of base/exp used."""
     n = base.shape[0] if n is None else n
     if out is None:
@@ -381,7 +383,7 @@ def modexp_ws(ctx, base, exp, exp_bits, ws, window=0, out=None, ctx_idx=None, pl
     if not ws.is_cuda or not ws.is_contiguous():
         raise ValueError("ws: expected a contiguous device tensor")
     flags = (_redc_flags(plain, cios) | _impl_flags(block) | (MX_ONE_LANE if one_lane else 0) |
-             (MX_TWO_LANES if two_lanes else 0))
+             (MX_TWO_LANES if two_lanes else 0) | (MX_FOUR_LANES if four_lanes else 0))
     _check(lib().modexp_batch_ws(ctx.handle, _ptr(ctx_idx), _ptr(base), _ptr(exp) if exp_bits else None,
                                  exp_bits, window, _ptr(out), n, flags, _ptr(ws), ws.numel() * ws.element_size(),
                                  _stream_ptr(stream)))

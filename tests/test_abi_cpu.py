@@ -67,10 +67,11 @@ def test_header_constants_match_the_binding():
     vals = dict((k, int(v)) for k, v in re.findall(r"\b(MX_[A-Z0-9_]+)\s*=\s*(\d+)", src))
     for name in ("MX_OK", "MX_EINVAL", "MX_ENOMEM", "MX_EDEVICE", "MX_EUNSUPPORTED", "MX_REDC_TRUNC",
                  "MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS", "MX_TWO_LANES",
-                 "MX_REDC_KARATSUBA", "MX_MUL_KARATSUBA2", "MX_CHECK_INPUTS"):
+                 "MX_REDC_KARATSUBA", "MX_MUL_KARATSUBA2", "MX_CHECK_INPUTS", "MX_FOUR_LANES"):
         assert vals[name] == getattr(montexp, name), name
     flags = [vals[k] for k in ("MX_REDC_PLAIN", "MX_IMPL_BLOCK", "MX_MUL_KARATSUBA", "MX_ONE_LANE", "MX_REDC_CIOS",
-                               "MX_TWO_LANES", "MX_REDC_KARATSUBA", "MX_MUL_KARATSUBA2", "MX_CHECK_INPUTS")]
+                               "MX_TWO_LANES", "MX_REDC_KARATSUBA", "MX_MUL_KARATSUBA2", "MX_CHECK_INPUTS",
+                               "MX_FOUR_LANES")]
     assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)
 
 

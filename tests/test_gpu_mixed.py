@@ -90,6 +90,9 @@ def test_block_kernel_one_two_and_four_lanes_per_instance_agree(mx):
     capped = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
                                 ctx_idx=idx, two_lanes=True))  # MX_TWO_LANES: two lanes where four would run
     assert capped == one[lo:hi]
+    four = dev_ints(mx.modexp(ctx, bd[lo2:].contiguous(), ed[lo2:].contiguous(), bits, window=3, block=True,
+                              ctx_idx=idx2, four_lanes=True))  # MX_FOUR_LANES: four lanes where two would run
+    assert four == one[lo2:]
     M, Bs, Es = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
     for i in (0, 32767, 32768, n - 1):
         assert one[i] == oracle.modexp(Bs[i], Es[i], M[i], bits)
@@ -227,10 +230,10 @@ def test_autotuned_plan_matches_single_class_and_oracle(mx, tmp_path):
     from paper_2410_18129_amd import autotune
     counts = {1024: 130, 2048: 70, 3072: 65, 4096: 71}
     waves = 32
-    # two candidates per large class keep the test short: one and two lanes per instance
+    # two candidates per large class keep the test short (one, two or four lanes per instance)
     cands = {1024: [(3, 0), (4, 0)], 2048: [(3, 0), (3, mx.MX_IMPL_BLOCK)],
-             3072: [(4, mx.MX_IMPL_BLOCK | mx.MX_ONE_LANE), (4, mx.MX_IMPL_BLOCK | mx.MX_TWO_LANES)],
-             4096: [(4, mx.MX_IMPL_BLOCK | mx.MX_ONE_LANE), (4, mx.MX_IMPL_BLOCK | mx.MX_TWO_LANES)]}
+             3072: [(4, mx.MX_IMPL_BLOCK | mx.MX_ONE_LANE), (4, mx.MX_IMPL_BLOCK | mx.MX_FOUR_LANES)],
+             4096: [(4, mx.MX_IMPL_BLOCK | mx.MX_TWO_LANES), (4, mx.MX_IMPL_BLOCK | mx.MX_FOUR_LANES)]}
     times = {b: autotune.measure_class(b, waves=waves, reps=1, candidates=c) for b, c in cands.items()}
     sched, span = autotune.choose(counts, times, waves)
     assert span > 0 and set(sched) == set(counts)
@@ -256,22 +259,36 @@ def test_autotuned_plan_matches_single_class_and_oracle(mx, tmp_path):
 
 
 def test_mixed_plan_lane_flags(mx):
-    """MX_ONE_LANE / MX_TWO_LANES pick the tile of a block batch (64 or 32 instances); two lanes exist for
-    the 3072- and 4096-bit schoolbook tiles only."""
+    """MX_ONE_LANE / MX_TWO_LANES / MX_FOUR_LANES pick the tile of a block batch (64, 32 or 16 instances; the
+    four-lane tiles keep their arrays in LDS); two and four lanes exist for the 3072- and 4096-bit schoolbook
+    tiles only.  Every choice gives the single-class results."""
     import torch
     counts = {3072: 65, 4096: 71}
     batches, _ = _mixed_inputs(mx, counts, k=13)
-    for flags, tiles in ((mx.MX_ONE_LANE, 2 + 2), (mx.MX_TWO_LANES, 3 + 3)):
+    alone = [dev_ints(mx.modexp(b["ctx"], b["base"], b["exp"], bits, window=4, one_lane=True))
+             for b, bits in zip(batches, counts)]
+    for flags, tiles in ((mx.MX_ONE_LANE, 2 + 2), (mx.MX_TWO_LANES, 3 + 3), (mx.MX_FOUR_LANES, 5 + 5)):
         for b in batches:
             b["flags"] = flags
+            b["window"] = 4
+            b["out"].zero_()
         plan = mx.MixedPlan(batches)
         assert plan.njobs == tiles
+        plan.launch()
+        torch.cuda.synchronize()
+        for b, want, bits in zip(batches, alone, counts):
+            assert dev_ints(b["out"]) == want, (bits, flags)
         plan.close()
     ctx = mx.Context(wl.random_moduli(wl.stream(15, "moduli"), 2048, 4), 2048)
     t = torch.zeros((4, ctx.words), dtype=torch.int64, device="cuda")
+    for flags in (mx.MX_TWO_LANES, mx.MX_FOUR_LANES):
+        with pytest.raises(mx.MontError) as ei:
+            mx.MixedPlan([{"ctx": ctx, "base": t, "exp": t, "exp_bits": 2048, "out": t, "flags": flags}])
+        assert ei.value.status == mx.MX_EUNSUPPORTED
     with pytest.raises(mx.MontError) as ei:
-        mx.MixedPlan([{"ctx": ctx, "base": t, "exp": t, "exp_bits": 2048, "out": t, "flags": mx.MX_TWO_LANES}])
-    assert ei.value.status == mx.MX_EUNSUPPORTED
+        mx.MixedPlan([{"ctx": ctx, "base": t, "exp": t, "exp_bits": 2048, "out": t,
+                       "flags": mx.MX_ONE_LANE | mx.MX_FOUR_LANES}])
+    assert ei.value.status == mx.MX_EINVAL
     ctx.close()
     for b in batches:
         b["ctx"].close()

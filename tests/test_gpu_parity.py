@@ -278,9 +278,11 @@ def test_errors_and_noops(mx):
     with pytest.raises(mx.MontError) as ei:
         mx.modexp(ctx, one, one, 8, plain=True, cios=True)
     assert ei.value.status == mx.MX_EINVAL
-    with pytest.raises(mx.MontError) as ei:  # MX_ONE_LANE and MX_TWO_LANES exclude each other
-        mx.modexp(ctx, one, one, 8, one_lane=True, two_lanes=True)
-    assert ei.value.status == mx.MX_EINVAL
+    for kw in ({"one_lane": True, "two_lanes": True}, {"one_lane": True, "four_lanes": True},
+               {"two_lanes": True, "four_lanes": True}):  # one lane choice at a time
+        with pytest.raises(mx.MontError) as ei:
+            mx.modexp(ctx, one, one, 8, **kw)
+        assert ei.value.status == mx.MX_EINVAL, kw
     with pytest.raises(mx.MontError) as ei:  # one reduction at a time
         mx.mont_sqr(ctx, a[:1], cios=True, kara_redc=True)
     assert ei.value.status == mx.MX_EINVAL
@@ -309,3 +311,12 @@ def test_errors_and_noops(mx):
             mx.modexp(c, xb, e1, 64, cios=True, block=block)
         assert ei.value.status == mx.MX_EUNSUPPORTED
         c.close()
+    # the Karatsuba-truncated reduction runs one lane per instance
+    c = mx.Context(_moduli(4096, 1, k=8), 4096)
+    xe = torch.zeros((1, c.words), dtype=torch.int64, device="cuda")
+    e1 = torch.zeros((1, 1), dtype=torch.int64, device="cuda")
+    for kw in ({"four_lanes": True}, {"two_lanes": True}):
+        with pytest.raises(mx.MontError) as ei:
+            mx.modexp(c, xe, e1, 64, kara_redc=True, **kw)
+        assert ei.value.status == mx.MX_EUNSUPPORTED, kw
+    c.close()
