@@ -389,41 +389,51 @@ __device__ __forceinline__ void scan_product(bool sqr, const LaneBuf& ws) {
   uint64_t cols[2 * H];
   sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
-  // pair i of diagonal c: (i, c - i), up to the middle for squares
-  auto next = [&](uint32_t c, uint32_t i, uint32_t& nc, uint32_t& ni) {
-    nc = c;
-    ni = i + 1;
+  uint32_t a[H], b[H];
+  ld_rows<H>(ws, Lay::Y, a);
+  ld_rows<H>(ws, rb, b);
+  uint32_t c = 0, i = 0;
+#pragma nounroll
+  for (;;) {
+    const uint32_t j = c - i;
+    uint32_t nc = c, ni = i + 1;
     if (ni > (c < K ? c : K - 1) || (sqr && ni > c - ni)) {
       nc = c + 1;
       ni = nc >= K ? nc - K + 1 : 0u;
     }
-    return nc < 2 * K - 1;
-  };
-  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[H]) {
-    ld_rows<H>(ws, Lay::Y + i * H, x);
-    ld_rows<H>(ws, rb + (c - i) * H, y);
-  };
-  auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[H]) {
-    if (sqr && 2 * i == c) {
+    const bool more = nc < 2 * K - 1;
+    uint32_t na[H], nb[H];
+    if (more) {
+      ld_rows<H>(ws, Lay::Y + ni * H, na);
+      ld_rows<H>(ws, rb + (nc - ni) * H, nb);
+    }
+    compiler_fence();
+    if (sqr && i == j) {
       uint32_t a2[H];
       sfor<0, H>([&](auto P) { a2[decltype(P)::value] = a[decltype(P)::value] << 1; });
-      blk_cols<H, 0, 2 * H - 2, true, RotMad>(cols, a, a2);
+      blk_cols<H, 0, 2 * H - 2, true>(cols, a, a2);
       sfor<0, H>([&](auto P) {
         constexpr int p = decltype(P)::value;
-        RotMad::template mac<p>(cols[2 * p], a[p], a[p]);
+        cols[2 * p] += (uint64_t)a[p] * a[p];
       });
     } else {
       if (sqr) sfor<0, H>([&](auto P) { b[decltype(P)::value] <<= 1; });
-      blk_cols<H, 0, 2 * H - 2, false, RotMad>(cols, a, b);
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
     }
     if (nc != c) {  // diagonal c done: block c of T is final
       uint32_t o[H];
       blk_emit<H>(cols, carry, o);
       st_rows<H>(ws, Lay::T + c * H, o);
     }
-    (void)more;
-  };
-  run_pairs<H, H>(0u, 0u, next, load, body);
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    i = ni;
+    sfor<0, H>([&](auto P) {
+      a[decltype(P)::value] = na[decltype(P)::value];
+      b[decltype(P)::value] = nb[decltype(P)::value];
+    });
+  }
   uint32_t o[H];
   blk_emit<H>(cols, carry, o);
   st_rows<H>(ws, Lay::T + (2 * K - 1) * H, o);
@@ -438,33 +448,42 @@ __device__ __forceinline__ void scan_q(const LaneBuf& ws, const LaneBuf& cnp) {
   uint64_t cols[2 * H];
   sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
   uint64_t carry = 0;
-  auto next = [&](uint32_t c, uint32_t i, uint32_t& nc, uint32_t& ni) {
-    nc = c;
-    ni = i + 1;
+  uint32_t a[H], b[H];
+  ld_rows<H>(ws, Lay::T, a);
+  ld_rows<H>(cnp, 0, b);
+  uint32_t c = 0, i = 0;
+#pragma nounroll
+  for (;;) {
+    uint32_t nc = c, ni = i + 1;
     if (ni > c) {
       nc = c + 1;
       ni = 0;
     }
-    return nc < K;
-  };
-  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[H]) {
-    ld_rows<H>(ws, Lay::T + i * H, x);
-    ld_rows<H>(cnp, (c - i) * H, y);
-  };
-  auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[H]) {
+    const bool more = nc < K;
+    uint32_t na[H], nb[H];
+    if (more) {
+      ld_rows<H>(ws, Lay::T + ni * H, na);
+      ld_rows<H>(cnp, (nc - ni) * H, nb);
+    }
+    compiler_fence();
     if (c + 1 < K)
-      blk_cols<H, 0, 2 * H - 2, false, RotMad>(cols, a, b);
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
     else
-      blk_cols<H, 0, H - 1, false, RotMad>(cols, a, b);
+      blk_cols<H, 0, H - 1, false>(cols, a, b);
     if (nc != c) {
       uint32_t o[H];
       blk_emit<H>(cols, carry, o);  // the carry out of block K-1 is dropped: mod R
       st_rows<H>(ws, Lay::Q + c * H, o);
     }
-    (void)i;
-    (void)more;
-  };
-  run_pairs<H, H>(0u, 0u, next, load, body);
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    i = ni;
+    sfor<0, H>([&](auto P) {
+      a[decltype(P)::value] = na[decltype(P)::value];
+      b[decltype(P)::value] = nb[decltype(P)::value];
+    });
+  }
 }
 
 // Y = (T + q N) / R (Algorithm 6 step 4 / Algorithm 3).  TRUNC (Theorem 2):
@@ -486,24 +505,31 @@ __device__ __forceinline__ void scan_qn(const LaneBuf& ws, const LaneBuf& cn) {
     for (uint32_t i = 0; i + 2 <= K; ++i)
       cols[H - 2] += (uint64_t)ws.ld(Lay::Q + i * H + H - 1) * cn.ld((K - 2 - i) * H + H - 1);
   }
-  auto next = [&](uint32_t c, uint32_t i, uint32_t& nc, uint32_t& ni) {
-    nc = c;
-    ni = i + 1;
+  uint32_t a[H], b[H];
+  {
+    const uint32_t i0 = c0 >= K ? c0 - K + 1 : 0u;
+    ld_rows<H>(ws, Lay::Q + i0 * H, a);
+    ld_rows<H>(cn, (c0 - i0) * H, b);
+  }
+  uint32_t c = c0, i = c0 >= K ? c0 - K + 1 : 0u;
+#pragma nounroll
+  for (;;) {
+    uint32_t nc = c, ni = i + 1;
     if (ni > (c < K ? c : K - 1)) {
       nc = c + 1;
       ni = nc >= K ? nc - K + 1 : 0u;
     }
-    return nc < 2 * K - 1;
-  };
-  auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[H]) {
-    ld_rows<H>(ws, Lay::Q + i * H, x);
-    ld_rows<H>(cn, (c - i) * H, y);
-  };
-  auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[H]) {
+    const bool more = nc < 2 * K - 1;
+    uint32_t na[H], nb[H];
+    if (more) {
+      ld_rows<H>(ws, Lay::Q + ni * H, na);
+      ld_rows<H>(cn, (nc - ni) * H, nb);
+    }
+    compiler_fence();
     if (TRUNC && c == K - 1)
-      blk_cols<H, H - 2, 2 * H - 2, false, RotMad>(cols, a, b);
+      blk_cols<H, H - 2, 2 * H - 2, false>(cols, a, b);
     else
-      blk_cols<H, 0, 2 * H - 2, false, RotMad>(cols, a, b);
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
     if (nc != c) {  // diagonal c done: add block c of T, then emit or fold the carry
       uint32_t tb[H];
       ld_rows<H>(ws, Lay::T + c * H, tb);
@@ -525,10 +551,15 @@ __device__ __forceinline__ void scan_qn(const LaneBuf& ws, const LaneBuf& cn) {
         st_rows<H>(ws, Lay::Y + (c - K) * H, o);
       }
     }
-    (void)i;
-    (void)more;
-  };
-  run_pairs<H, H>(c0, c0 >= K ? c0 - K + 1 : 0u, next, load, body);
+    compiler_fence();
+    if (!more) break;
+    c = nc;
+    i = ni;
+    sfor<0, H>([&](auto P) {
+      a[decltype(P)::value] = na[decltype(P)::value];
+      b[decltype(P)::value] = nb[decltype(P)::value];
+    });
+  }
   // the top block: columns (2K-1) H .. 2n-1 and T's top limbs
   uint32_t tb[H];
   ld_rows<H>(ws, Lay::T + (2 * K - 1) * H, tb);
@@ -915,8 +946,10 @@ __device__ __forceinline__ void scang_q(const WB& ws, const LaneBuf& cnp) {
     return nc < K;
   };
   auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[NB]) {
-    ld_rows<H>(ws, Lay::T + i * H, x);
-    ld_shift<H, LP>(cnp, (c - i) * H, r, rl, y);
+    // N' block as the unshifted operand: its reads are the same row in every lane of a group (one line
+    // per read), while the shifted reads, four rows per group, go to the lane's arrays
+    ld_rows<H>(cnp, (c - i) * H, x);
+    ld_shift<H, LP>(ws, Lay::T + i * H, r, rl, y);
   };
   auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[NB]) {
     res_mask<H, LP>(rl, b);
@@ -980,8 +1013,8 @@ __device__ __forceinline__ void scang_qn(const WB& ws, const LaneBuf& cn) {
     return nc < 2 * K - 1;
   };
   auto load = [&](uint32_t c, uint32_t i, uint32_t (&x)[H], uint32_t (&y)[NB]) {
-    ld_rows<H>(ws, kQrows<H, K>() + i * H, x);
-    ld_shift<H, LP>(cn, (c - i) * H, r, rl, y);
+    ld_rows<H>(cn, (c - i) * H, x);  // the modulus block unshifted, as N' in scang_q
+    ld_shift<H, LP>(ws, kQrows<H, K>() + i * H, r, rl, y);
   };
   auto body = [&](uint32_t c, uint32_t i, uint32_t nc, bool more, uint32_t (&a)[H], uint32_t (&b)[NB]) {
     res_mask<H, LP>(rl, b);
