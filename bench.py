@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--only", choices=("headline", "c3"), default=None,
                     help="one launch configuration alone, for profiling: the headline exponentiation (window "
                          "--window) or the 16384 x 4096-bit block exponentiation at window 6")
+    ap.add_argument("--plain", action="store_true",
+                    help="with --only headline: the plain reduction (Algorithm 3) instead of the truncated one")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device-to-device three times (calibrates FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -306,9 +308,10 @@ def only_line(a, mx, counts, dev, stream):
     """One configuration's launches alone (for a profiler run): prints its kernel time per launch."""
     if a.only == "headline":
         b = Batch(mx, a.bits, a.batch, 2, dev)
-        fn = lambda: mx.modexp(b.ctx, b.base, b.exp, a.bits, window=a.window, out=b.out, stream=stream)
-        work = counts.modexp_products(a.bits, a.bits, a.window) * b.n
-        name = "%d x %d-bit modexp, window %d" % (b.n, a.bits, a.window)
+        fn = lambda: mx.modexp(b.ctx, b.base, b.exp, a.bits, window=a.window, out=b.out, plain=a.plain,
+                               stream=stream)
+        work = counts.modexp_products(a.bits, a.bits, a.window) * b.n  # the truncated method's products
+        name = "%d x %d-bit modexp, window %d%s" % (b.n, a.bits, a.window, ", plain reduction" if a.plain else "")
     else:
         b = Batch(mx, 4096, 16384, 3, dev)
         fn = lambda: mx.modexp(b.ctx, b.base, b.exp, 4096, window=6, out=b.out, block=True, stream=stream)
@@ -399,6 +402,11 @@ def other_workloads(a, mx, counts, dev, stream):
     c3["modexp_per_s_kara_redc_one_lane"] = b3.n * 2 / wl_
     c3["schoolbook_vs_kara_redc_one_lane"] = (c3["modexp_per_s_schoolbook_one_lane"] /
                                               c3["modexp_per_s_kara_redc_one_lane"])
+    # word-interleaved Montgomery multiplication (Algorithm 4) with 37-limb words, one lane per instance (row f1)
+    wl_, k = time_launches(lambda: mx.modexp(b3.ctx, b3.base, b3.exp, 4096, window=6, out=b3.out, cios=True,
+                                             stream=stream), 2, 1, stream)
+    c3["modexp_per_s_cios_one_lane"] = b3.n * 2 / wl_
+    c3["schoolbook_vs_cios_one_lane"] = c3["modexp_per_s_schoolbook_one_lane"] / c3["modexp_per_s_cios_one_lane"]
     # raw products at Table 6's largest sizes (limb counts 147 and 149), schoolbook and Karatsuba at one
     # and two levels, 16384 seeded instances each
     g = wl.stream(3, "ops_a")

@@ -87,9 +87,12 @@ enum {
   MX_REDC_CIOS = 16,   /* word-interleaved Montgomery multiplication (Section
                           4, Algorithm 4, CIOS): for each limb a_i, Y += a_i B,
                           q_i = Y_0 N'_0 mod 2^28, Y = (Y + q_i N) / 2^28;
-                          same results.  Register-resident classes (<= 2048
-                          bits) only, else MX_EUNSUPPORTED; with MX_REDC_PLAIN,
-                          MX_EINVAL; not in the mixed launch                 */
+                          same results.  The register-resident classes (<=
+                          2048 bits, their default kernels); above 2048 bits
+                          the same steps with 37-limb blocks as the words, one
+                          lane per instance (MX_TWO_LANES, MX_FOUR_LANES:
+                          MX_EUNSUPPORTED); with MX_REDC_PLAIN, MX_EINVAL; not
+                          in the mixed launch                                */
   MX_TWO_LANES = 32,   /* exponentiation with the block kernels: at most two
                           lanes per instance (batches of at most 16384 would
                           otherwise run four); a middle ground between latency

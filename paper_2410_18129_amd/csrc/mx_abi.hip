@@ -190,13 +190,19 @@ static int redc_of(uint32_t flags) {
 static mx_status check_redc(const char* name, const mont_ctx* ctx, int impl, int redc) {
   if (redc < 0)
     return fail(MX_EINVAL, "%s: MX_REDC_PLAIN, MX_REDC_CIOS and MX_REDC_KARATSUBA exclude each other", name);
-  if (redc == mx::kRedcCios && (impl != 0 || !ctx->ops->has_cios))
-    return fail(MX_EUNSUPPORTED, "%s: MX_REDC_CIOS is built for the register-resident kernels (<= 2048 bits) only",
-                name);
+  const bool regcls = ctx->bits <= 2048;  // the classes with register-resident kernels
+  if (redc == mx::kRedcCios) {
+    // register-resident kernels; above 2048 bits the block-word CIOS, one lane per instance
+    const bool reg = regcls && impl == 0;
+    const bool blk = !regcls && (impl == 0 || impl == 1 || impl == 3);
+    if (!ctx->ops->has_cios || (!reg && !blk))
+      return fail(MX_EUNSUPPORTED, "%s: MX_REDC_CIOS is built for the register-resident kernels (<= 2048 bits) and "
+                  "the block classes with one lane per instance", name);
+  }
   if (redc == mx::kRedcKara) {
-    const bool reg = impl == 0 && ctx->ops->has_cios;
+    const bool reg = regcls && impl == 0;
     // block kernels (the only ones above 2048 bits), one lane per instance, an even block count
-    const bool blk = (impl >= 1 || ctx->bits > 2048) && impl != 4 && impl != 5 && ctx->ops->has_kara;
+    const bool blk = (impl >= 1 || !regcls) && impl != 4 && impl != 5 && ctx->ops->has_kara;
     if (!reg && !blk)
       return fail(MX_EUNSUPPORTED, "%s: MX_REDC_KARATSUBA is built for the register-resident kernels and the block "
                   "kernels with an even block count (2048, 4096 bits), one lane per instance", name);

@@ -1046,15 +1046,128 @@ __device__ __forceinline__ void scang_qn(const WB& ws, const LaneBuf& cn) {
   st_rows<H>(ws, Lay::Y + (K - 1) * H, o);
 }
 
+// ---- word-interleaved Montgomery multiplication at block level (Section 4, Algorithm 4) ----
+//
+// CIOS with 37-limb blocks as its words, W = 2^(28 H): for each block a_i of the first operand,
+// T = Z + a_i B, q_i = (T mod W) N'_0 mod W with N'_0 = N' mod W = -N^{-1} mod W, and
+// Z = (T + q_i N) / W, the low block of T + q_i N vanishing.  The q_i are the blocks of the unique
+// q = -A B N^{-1} mod R, so after K steps Z = (A B + q N) / R: the other reductions' integer.  Each
+// step runs over the output blocks c with one 64-bit column window (blk_cols, 2H columns): block c
+// collects Z_c and the low halves of a_i B_c and q_i N_c, the high halves of a_i B_{c-1} and
+// q_i N_{c-1}; block 0's low half gives q_i first.  A column collects at most 4 H products below 2^56
+// plus a limb and a carry, within 64 bits.  Products per operation: 2 K^2 block products and K
+// half-block products for the q_i -- the same for a square (no symmetry to use).  Z (n + 1 limbs,
+// below 3N < R, so its top limb stays 0) lives in the S rows; the last step writes the result over
+// Y, whose blocks it has read by then.  One lane per instance.
+template <int H, int K>
+__device__ __forceinline__ void scan_cios(bool sqr, const LaneBuf& ws, const LaneBuf& cn, const LaneBuf& cnp) {
+  using Lay = BlkLayout<H, K>;
+  constexpr uint32_t n = Lay::n, Z = Lay::S;
+  const uint32_t rb = sqr ? Lay::Y : Lay::B;
+  zero_rows(ws, Z, n + 1);
+#pragma nounroll
+  for (uint32_t i = 0; i < K; ++i) {
+    const uint32_t dst = i + 1 == K ? Lay::Y : Z;
+    uint32_t a[H], q[H];
+    ld_rows<H>(ws, Lay::Y + i * H, a);
+    uint64_t cols[2 * H];
+    sfor<0, 2 * H>([&](auto L) { cols[decltype(L)::value] = 0; });
+    uint64_t carry = 0;
+    {  // block 0: T's low block, q_i, and the vanishing low block of T + q_i N
+      uint32_t b[H], z[H];
+      ld_rows<H>(ws, rb, b);
+      ld_rows<H>(ws, Z, z);
+      compiler_fence();
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+      sfor<0, H>([&](auto D) { cols[decltype(D)::value] += z[decltype(D)::value]; });
+      uint32_t t0[H];  // T mod W
+      uint64_t c = 0;
+      sfor<0, H>([&](auto D) {
+        constexpr int d = decltype(D)::value;
+        const uint64_t v = cols[d] + c;
+        t0[d] = (uint32_t)v & kLimbMask;
+        c = v >> kLimbBits;
+      });
+      uint32_t np0[H];
+      ld_rows<H>(cnp, 0, np0);
+      compiler_fence();
+      uint64_t qc[H];
+      sfor<0, H>([&](auto D) { qc[decltype(D)::value] = 0; });
+      blk_cols<H, 0, H - 1, false>(qc, t0, np0);  // q_i = t0 N'_0 mod W: the low half only
+      c = 0;
+      sfor<0, H>([&](auto D) {
+        constexpr int d = decltype(D)::value;
+        const uint64_t v = qc[d] + c;
+        q[d] = (uint32_t)v & kLimbMask;
+        c = v >> kLimbBits;
+      });
+      uint32_t m[H];
+      ld_rows<H>(cn, 0, m);
+      compiler_fence();
+      blk_cols<H, 0, 2 * H - 2, false>(cols, q, m);
+      sfor<0, H>([&](auto D) {  // limbs 0 (T + q_i N = 0 mod W): only the carry goes on
+        constexpr int d = decltype(D)::value;
+        carry = (cols[d] + carry) >> kLimbBits;
+        cols[d] = cols[d + H];
+        cols[d + H] = 0;
+      });
+    }
+    uint32_t b[H], m[H], z[H];
+    if (K > 1) {
+      ld_rows<H>(ws, rb + H, b);
+      ld_rows<H>(cn, H, m);
+      ld_rows<H>(ws, Z + H, z);
+    }
+#pragma nounroll
+    for (uint32_t c = 1; c < K; ++c) {
+      uint32_t nb[H], nm[H], nz[H];
+      const bool more = c + 1 < K;
+      if (more) {
+        ld_rows<H>(ws, rb + (c + 1) * H, nb);
+        ld_rows<H>(cn, (c + 1) * H, nm);
+        ld_rows<H>(ws, Z + (c + 1) * H, nz);
+      }
+      compiler_fence();
+      blk_cols<H, 0, 2 * H - 2, false>(cols, a, b);
+      blk_cols<H, 0, 2 * H - 2, false>(cols, q, m);
+      sfor<0, H>([&](auto D) { cols[decltype(D)::value] += z[decltype(D)::value]; });
+      uint32_t o[H];
+      blk_emit<H>(cols, carry, o);
+      st_rows<H>(ws, dst + (c - 1) * H, o);  // Z_{c-1}, read at c - 1, or Y's block c - 1, read by now
+      compiler_fence();
+      if (more) {
+        sfor<0, H>([&](auto P) {
+          constexpr int p = decltype(P)::value;
+          b[p] = nb[p];
+          m[p] = nm[p];
+          z[p] = nz[p];
+        });
+      }
+    }
+    // the top block: the high halves of a_i B_{K-1} and q_i N_{K-1}, Z's top limb
+    cols[0] += ws.ld(Z + n);
+    uint32_t o[H];
+    blk_emit<H>(cols, carry, o);
+    st_rows<H>(ws, dst + (K - 1) * H, o);
+    if (i + 1 < K) ws.st(Z + n, (uint32_t)carry);  // 0 (Z < 3N < R); the result has n limbs
+    compiler_fence();
+  }
+}
+
 // One Montgomery product on the workspace: Y <- REDC(Y * B) or REDC(Y^2).
 // n = K H; context blocks come from the limb-major context arrays.  LP lanes
 // per instance (1, or 2 or 4 for the schoolbook product).
 // KREDC: the truncated q N by one-level Karatsuba (scan_qn_kara; one lane per instance, K even).
-template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false, typename WB>
+// BCIOS: block-word CIOS (scan_cios; one lane per instance).
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false, bool BCIOS = false,
+          typename WB>
 __device__ __forceinline__ void mont_blk(bool sqr, const WB& ws, const LaneBuf& cn, const LaneBuf& cnp) {
   static_assert(LP == 1 || ((LP == 2 || LP == 4) && !KARA), "several lanes per instance: schoolbook products only");
   static_assert(!KREDC || (LP == 1 && TRUNC && K % 2 == 0), "Karatsuba-truncated q N: one lane, even block count");
-  if constexpr (LP > 1) {
+  static_assert(!BCIOS || (LP == 1 && !KARA && !KREDC), "block-word CIOS: one lane, its own products");
+  if constexpr (BCIOS) {
+    scan_cios<H, K>(sqr, ws, cn, cnp);
+  } else if constexpr (LP > 1) {
     scang_product<H, K, LP>(sqr, ws);
     scang_q<H, K, LP>(ws, cnp);
     scang_qn<H, K, TRUNC, LP>(ws, cn);
@@ -1108,7 +1221,7 @@ __device__ __forceinline__ void contract_rows(const Buf& ws, uint32_t row, uint6
 }
 
 // ---- batched modmul / modsqr, block version ---------------------------------
-template <int H, int K, bool TRUNC, bool SQR, bool KARA = false, bool KREDC = false>
+template <int H, int K, bool TRUNC, bool SQR, bool KARA = false, bool KREDC = false, bool BCIOS = false>
 __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                  const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
                                                  uint64_t* __restrict__ out, uint32_t count, uint32_t* ws_base,
@@ -1129,7 +1242,7 @@ __global__ void __launch_bounds__(64) k_mont_blk(CtxDev ctx, const uint32_t* __r
   const LaneBuf cnp{make_buf(ctx.np, cbytes), c * 4u, ctx.stride * 4u};
   expand_rows<H, K>(ws, Lay::Y, a + (size_t)inst * rw, rw);
   if (!SQR) expand_rows<H, K>(ws, Lay::B, b + (size_t)inst * rw, rw);
-  mont_blk<H, K, TRUNC, KARA, 1, KREDC>(SQR, ws, cn, cnp);
+  mont_blk<H, K, TRUNC, KARA, 1, KREDC, BCIOS>(SQR, ws, cn, cnp);
   if (live) contract_rows<H, K>(ws, Lay::Y, out + (size_t)inst * rw, rw);
 }
 
@@ -1174,7 +1287,8 @@ __device__ __forceinline__ void copy_rows_split(const DB& d, uint32_t dr, const 
   }
 }
 
-template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false, bool LDSHOT = false>
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false, bool LDSHOT = false,
+          bool BCIOS = false>
 __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_t* __restrict__ cidx,
                                                 const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                 uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
@@ -1303,7 +1417,7 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
       for (uint32_t i = 0; i < n; ++i) hot.st(Lay::B + i, i == 0 ? 1u : 0u);
     }
     compiler_fence();
-    mont_blk<H, K, TRUNC, KARA, LP, KREDC>(kind == kSqr, hot, cn, cnp);
+    mont_blk<H, K, TRUNC, KARA, LP, KREDC, BCIOS>(kind == kSqr, hot, cn, cnp);
     compiler_fence();
     if (store_e >= 0) copy_rows_split<SP, n>(ws, Lay::G + (uint32_t)store_e * n, hot, Lay::Y, rs);
   }
@@ -1324,7 +1438,7 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
   if (writer) contract_rows<H, K>(hot, Lay::B, out + (size_t)inst * bw, bw);
 }
 
-template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false>
+template <int H, int K, bool TRUNC, bool KARA = false, int LP = 1, bool KREDC = false, bool BCIOS = false>
 __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* __restrict__ cidx,
                                                    const uint64_t* __restrict__ base, const uint64_t* __restrict__ ex,
                                                    uint32_t ebits, uint32_t ewords, uint32_t w, uint32_t bw,
@@ -1336,7 +1450,7 @@ __global__ void __launch_bounds__(64) k_modexp_blk(CtxDev ctx, const uint32_t* _
   stagger<H * K>(blockIdx.x, w);
   constexpr bool kLds = LP == 4;  // 4n rows of 16 words: 37.9 KB at 4096 bits, four wavefronts per CU
   __shared__ uint32_t s_hot[kLds ? 4 * H * K * (64 / LP) : 1];
-  modexp_tile_blk<H, K, TRUNC, KARA, LP, KREDC, kLds>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
+  modexp_tile_blk<H, K, TRUNC, KARA, LP, KREDC, kLds, BCIOS>(ctx, cidx, base, ex, ebits, ewords, w, bw, out, count,
                                                       ws_base + (size_t)blockIdx.x * (tbytes / 4u), tbytes, coff,
                                                       tile0, s_hot);
 }

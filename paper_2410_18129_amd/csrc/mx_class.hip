@@ -166,6 +166,17 @@ hipError_t mont_fn(int impl, int redc, bool sqr, const CtxDev& ctx, const uint32
   const bool trunc = redc == kRedcTrunc;
   // every block's region must lie in ws: checked here, before anything is enqueued
   if ((uint64_t)ws_rows_fn(impl, false, 0) * 256u * blocks > ws_bytes) return hipErrorInvalidValue;
+  if constexpr (kBlock) {  // block-word CIOS (Algorithm 4 with 37-limb words), one lane per instance
+    if (redc == kRedcCios) {
+      if (sqr)
+        hipLaunchKernelGGL((k_mont_blk<kH, kK, false, true, false, false, true>), dim3(blocks), dim3(64), 0, st,
+                           ctx, cidx, a, b, out, count, ws, ws_bytes, coff);
+      else
+        hipLaunchKernelGGL((k_mont_blk<kH, kK, false, false, false, false, true>), dim3(blocks), dim3(64), 0, st,
+                           ctx, cidx, a, b, out, count, ws, ws_bytes, coff);
+      return hipGetLastError();
+    }
+  }
   if constexpr (kHasKara) {
     // block kernels with the Karatsuba-truncated q N (one lane per instance); impl 2 also forms the
     // product by Karatsuba
@@ -240,6 +251,13 @@ hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx
   // every block's region must lie in ws (with LP lanes per instance a block's region is 1/LP of a
   // 64-instance tile's): checked here, before anything is enqueued
   if ((uint64_t)ws_rows_fn(impl, true, w) * 256u * blocks > ws_bytes) return hipErrorInvalidValue;
+  if constexpr (kBlock) {  // block-word CIOS, one lane per instance
+    if (redc == kRedcCios) {
+      hipLaunchKernelGGL((k_modexp_blk<kH, kK, false, false, 1, false, true>), dim3(blocks), dim3(64), 0, st, ctx,
+                         cidx, base, ex, ebits, ewords, w, (uint32_t)kW, out, count, ws, ws_bytes, coff);
+      return hipGetLastError();
+    }
+  }
   if constexpr (kHasKara) {
     // block kernels with the Karatsuba-truncated q N: one lane per instance
     if (redc == kRedcKara && (kBlock || impl >= 1)) {
@@ -342,7 +360,8 @@ hipError_t modexp_pair_fn(bool trunc, const CtxDev& c0, const CtxDev& c1, const 
   return hipErrorInvalidValue;
 }
 
-const ClassOps kOps = {kBits, kN, kHasBlk || kBlock, kHasKara, !kBlock, ctx_fn, ws_rows_fn, mont_fn, modexp_fn,
+// has_cios: word-interleaved products in the register-resident classes, block-word CIOS above 2048 bits
+const ClassOps kOps = {kBits, kN, kHasBlk || kBlock, kHasKara, true, ctx_fn, ws_rows_fn, mont_fn, modexp_fn,
                        kTwoWaves ? modexp_pair_fn : nullptr};
 
 }  // namespace

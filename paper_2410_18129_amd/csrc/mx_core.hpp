@@ -275,8 +275,9 @@ __device__ __forceinline__ void sqr_sb(const uint32_t (&a)[N], uint32_t (&t)[2 *
 //   smaller than 2^56 below column n-2, and limbs 0..n-1 of T + qN vanish
 //   (Theorem 1, equation (3)), so k = ceil((a1 2^28 + a2 mod 2^28) / 2^56).
 //   The indicator is the analogue of c_add (equation (1)).
-// PLAIN: the whole product T + q N is formed (Algorithm 3, B_fma) and the
-//   carry out of the low n limbs is propagated.
+// PLAIN: every partial product of q N is formed (Algorithm 3, B_fma); the
+//   carry out of the low n limbs is floor(L/R) + [T mod R != 0] with L the
+//   low columns of q N (Theorem 1's form with the whole q N).
 // C = floor(T / R) + sum_{w >= n} P_w 2^{28 (w - n)} + k   (Algorithm 6, step 4)
 //
 // The modulus limbs m[j] and N' limbs np[j] come from LDS (lane-private
@@ -288,10 +289,10 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
   constexpr int BK = kColBlock;
   uint32_t q[N];
   // q = T_lo * N' mod R: columns 0 .. N-1, column k = sum_{i<=k} t[i] np[k-i].
-  // PLAIN: as soon as a block of q is known, the same columns of T + q N are
-  // formed too (they need q_0 .. q_k only); they vanish mod 2^28 and pass on
-  // their carry, and each limb of T_lo is dead once its column is done.
   uint64_t carry = 0, lcarry = 0;
+  uint32_t nz = 0;  // PLAIN: T_lo != 0
+  if constexpr (!TRUNC) sfor<0, N>([&](auto I) { nz |= t[decltype(I)::value]; });
+  (void)nz;
   sfor<0, (N + BK - 1) / BK>([&](auto B) {
     constexpr int k0 = decltype(B)::value * BK;
     constexpr int bk = (N - k0) < BK ? (N - k0) : BK;
@@ -304,14 +305,25 @@ __device__ __forceinline__ void redc_blk(const uint32_t (&t)[2 * N], LoadM&& ldm
       q[k0 + d] = (uint32_t)v & kLimbMask;
       carry = v >> kLimbBits;
     });
-    if constexpr (!TRUNC) {
-      compiler_fence();
-      sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = t[k0 + decltype(D)::value]; });
-      colblock_ld<k0, bk, 0, N - 1, 0, N - 1, M>(q, ldm, acc);
-      sfor<0, bk>([&](auto D) { lcarry = (acc[decltype(D)::value] + lcarry) >> kLimbBits; });
-    }
     compiler_fence();
   });
+  // PLAIN: every product of q N, the low ones (columns below n, their sum L) after q.  The low n limbs
+  // of T + q N vanish, so the carry into limb n is (T_lo + L) / R = floor(L / R) + [T_lo != 0]
+  // (T_lo + (L mod R) is 0 or R, and 0 only when T_lo = 0, hence q = 0 and L = 0): Theorem 1's
+  // floor(T/R) + floor(qN/R) + c_add with the whole q N.  Normalising L's columns gives floor(L / R),
+  // and T_lo is dead once q is formed.
+  if constexpr (!TRUNC) {
+    sfor<0, (N + BK - 1) / BK>([&](auto B) {
+      constexpr int k0 = decltype(B)::value * BK;
+      constexpr int bk = (N - k0) < BK ? (N - k0) : BK;
+      uint64_t acc[bk];
+      sfor<0, bk>([&](auto D) { acc[decltype(D)::value] = 0; });
+      colblock_ld<k0, bk, 0, N - 1, 0, N - 1, M>(q, ldm, acc);
+      sfor<0, bk>([&](auto D) { lcarry = (acc[decltype(D)::value] + lcarry) >> kLimbBits; });
+      compiler_fence();
+    });
+    lcarry += nz != 0u ? 1u : 0u;
+  }
   // q * N: columns from n-2 (truncated, Theorem 2) or n (plain, the low
   // columns are done) to 2n-2
   constexpr int W0 = TRUNC ? N - 2 : N;

@@ -23,7 +23,8 @@ struct CtxDev {
 // impl: 0 = the class's default kernels, 1 = block-level schoolbook over
 // 37-limb blocks (available when has_block; the default above 2048 bits),
 // 2 = block kernels with a one-level Karatsuba product (when has_kara).
-// redc: one of Redc below; kRedcCios and kRedcKara only with impl 0 and has_cios.
+// redc: one of Redc below; kRedcCios with has_cios (impl 0 in the register-resident classes, the
+// block-word CIOS with one lane per instance above 2048 bits); kRedcKara as the ABI checks.
 enum Redc : int { kRedcTrunc = 0, kRedcPlain = 1, kRedcCios = 2, kRedcKara = 3 };
 struct ClassOps {
   int bits;

@@ -33,12 +33,11 @@ def _moduli(bits, count, k=1):
 
 
 def _redcs(bits):
-    """Reductions built for a class: truncated (Algorithm 6), plain (Algorithm 3) and, up to 2048 bits,
-    the word-interleaved CIOS (Algorithm 4) and the truncated high half of q*N formed by one-level
-    Karatsuba (Section 5); as keyword arguments of the binding."""
-    r = {"trunc": {}, "plain": {"plain": True}}
-    if bits <= 2048:
-        r["cios"] = {"cios": True}
+    """Reductions built for a class: truncated (Algorithm 6), plain (Algorithm 3), the word-interleaved
+    CIOS (Algorithm 4; above 2048 bits with 37-limb words) and, but for the odd block count of 3072 bits,
+    the truncated high half of q*N formed by one-level Karatsuba (Section 5); as keyword arguments of the
+    binding."""
+    r = {"trunc": {}, "plain": {"plain": True}, "cios": {"cios": True}}
     if bits != 3072:  # the block classes need an even block count (4096: four blocks of 37 limbs)
         r["kara"] = {"kara_redc": True}
     return r
@@ -293,8 +292,9 @@ def test_errors_and_noops(mx):
                                  8, 0, ctypes.c_void_p(ob.data_ptr()), 1, mx.MX_REDC_KARATSUBA | mx.MX_REDC_CIOS,
                                  None) == mx.MX_EINVAL
     ctx.close()
-    # CIOS exists for the register-resident kernels only: not for the block kernels or above 2048 bits
-    for bits, block in ((2048, True), (3072, False)):
+    # CIOS exists for the register-resident kernels and the block classes' one-lane kernels: not for the
+    # block kernels of 2048 bits
+    for bits, block in ((2048, True),):
         m = _moduli(bits, 1, k=8)
         c = mx.Context(m, bits)
         x = torch.zeros((1, c.mont_words), dtype=torch.int64, device="cuda")
@@ -311,12 +311,17 @@ def test_errors_and_noops(mx):
             mx.modexp(c, xb, e1, 64, cios=True, block=block)
         assert ei.value.status == mx.MX_EUNSUPPORTED
         c.close()
-    # the Karatsuba-truncated reduction runs one lane per instance
+    # the Karatsuba-truncated reduction and the block-word CIOS run one lane per instance
     c = mx.Context(_moduli(4096, 1, k=8), 4096)
     xe = torch.zeros((1, c.words), dtype=torch.int64, device="cuda")
     e1 = torch.zeros((1, 1), dtype=torch.int64, device="cuda")
-    for kw in ({"four_lanes": True}, {"two_lanes": True}):
-        with pytest.raises(mx.MontError) as ei:
-            mx.modexp(c, xe, e1, 64, kara_redc=True, **kw)
-        assert ei.value.status == mx.MX_EUNSUPPORTED, kw
+    for red in ({"kara_redc": True}, {"cios": True}):
+        for kw in ({"four_lanes": True}, {"two_lanes": True}):
+            with pytest.raises(mx.MontError) as ei:
+                mx.modexp(c, xe, e1, 64, **red, **kw)
+            assert ei.value.status == mx.MX_EUNSUPPORTED, (red, kw)
+    with pytest.raises(mx.MontError) as ei:  # no Karatsuba product with CIOS
+        mx.mont_sqr(c, torch.zeros((1, c.mont_words), dtype=torch.int64, device="cuda"), cios=True,
+                    block="karatsuba")
+    assert ei.value.status == mx.MX_EUNSUPPORTED
     c.close()

@@ -150,6 +150,8 @@ def test_16384_x_4096_w6_schoolbook_and_karatsuba(mx):
     sb = mx.modexp(ctx, b, e, bits, window=6, block=True).cpu().numpy()
     ka = mx.modexp(ctx, b, e, bits, window=6, block="karatsuba").cpu().numpy()
     assert np.array_equal(sb, ka)
+    ci = mx.modexp(ctx, b, e, bits, window=6, cios=True).cpu().numpy()  # block-word CIOS
+    assert np.array_equal(sb, ci)
     idx = _c3_idx()
     _oracle_check(sb, "c3", idx, lambda: _jobs(bits, n, k, idx), "16384 x 4096 w6")
     ctx.close()
