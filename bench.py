@@ -370,7 +370,10 @@ def other_workloads(a, mx, counts, dev, stream):
     # ---- config 1: 8 x 1024-bit ------------------------------------------------
     b1 = Batch(mx, 1024, 8, 1, dev)
     c1 = {}
-    for tag, kw in (("trunc", {}), ("plain", {"plain": True}), ("cios", {"cios": True})):
+    # the latency of one exponentiation: one lane per instance (register-resident), or four lanes per
+    # instance (the block kernel with its arrays in LDS)
+    for tag, kw in (("trunc", {}), ("plain", {"plain": True}), ("cios", {"cios": True}),
+                    ("trunc_four_lanes", {"block": True})):
         wl_, k = time_launches(lambda: mx.modexp(b1.ctx, b1.base, b1.exp, 1024, window=5, out=b1.out, stream=stream,
                                                  **kw), 5, 2, stream)
         c1["modexp_ms_" + tag] = min(k)
