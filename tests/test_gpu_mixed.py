@@ -99,6 +99,28 @@ def test_block_kernel_one_two_and_four_lanes_per_instance_agree(mx):
     ctx.close()
 
 
+@pytest.mark.parametrize("bits", [2048, 3072])
+def test_four_lane_block_kernel_matches_register_or_one_lane(mx, bits):
+    """The four-lane block kernel (columns split by residue, arrays in LDS) at 2048 bits (two blocks) and
+    3072 bits (three: a limb count that is not a multiple of four, so the split table scan masks its last
+    limbs) gives the register-resident kernel's (2048) or the one-lane block kernel's (3072) results on a
+    batch with a ragged tail, and the oracle's on samples."""
+    n = 200
+    mods = wl.random_moduli(wl.stream(17, "moduli"), bits, n)
+    ctx = mx.Context(mods, bits)
+    base = wl.random_below_fast(wl.stream(17, "bases"), mods, bits)
+    exps = wl.random_exponents(wl.stream(17, "exps"), bits, n)
+    bd, ed = mx.to_device(base), mx.to_device(exps)
+    four = dev_ints(mx.modexp(ctx, bd, ed, bits, window=4, block=True, four_lanes=True))
+    ref = dev_ints(mx.modexp(ctx, bd, ed, bits, window=4) if bits == 2048 else
+                   mx.modexp(ctx, bd, ed, bits, window=4, one_lane=True))
+    assert four == ref
+    M, Bs, Es = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
+    for i in (0, 15, 16, 101, n - 1):
+        assert four[i] == oracle.modexp(Bs[i], Es[i], M[i], bits), i
+    ctx.close()
+
+
 def test_block_flag_unsupported_class(mx):
     ctx = mx.Context(wl.random_moduli(wl.stream(12, "moduli"), 256, 1), 256)
     a = ints_dev([1], ctx.mont_words)
