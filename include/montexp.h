@@ -80,10 +80,9 @@ enum {
                            2048 and 4096 bits; same results                  */
   MX_ONE_LANE = 8,     /* exponentiation with the block kernels: one lane per
                           instance even for batches of at most 32768 (which
-                          otherwise run four lanes per instance up to 16384
-                          and two up to 32768: lower latency, more lanes); for
-                          loaded devices where throughput matters more than
-                          latency; same results                              */
+                          otherwise run four lanes per instance: lower
+                          latency, more lanes); for loaded devices where the
+                          other work fills the SIMDs; same results           */
   MX_REDC_CIOS = 16,   /* word-interleaved Montgomery multiplication (Section
                           4, Algorithm 4, CIOS): for each limb a_i, Y += a_i B,
                           q_i = Y_0 N'_0 mod 2^28, Y = (Y + q_i N) / 2^28;
@@ -94,14 +93,13 @@ enum {
                           MX_EUNSUPPORTED); with MX_REDC_PLAIN, MX_EINVAL; not
                           in the mixed launch                                */
   MX_TWO_LANES = 32,   /* exponentiation with the block kernels: at most two
-                          lanes per instance (batches of at most 16384 would
-                          otherwise run four); a middle ground between latency
-                          and throughput for a moderately loaded device; with
-                          MX_ONE_LANE, MX_EINVAL; same results               */
+                          lanes per instance (batches of at most 32768 would
+                          otherwise run four); with MX_ONE_LANE, MX_EINVAL;
+                          same results                                       */
   MX_MUL_KARATSUBA2 = 128, /* mp_mul_batch only: Karatsuba at two levels         */
   MX_FOUR_LANES = 512, /* exponentiation with the block schoolbook kernels: four
                           lanes per instance at any batch size (the default
-                          only up to 16384), the lanes' arrays in LDS; in the
+                          only up to 32768), the lanes' arrays in LDS; in the
                           mixed launch, 3072- and 4096-bit tiles of 16
                           instances; with MX_ONE_LANE or MX_TWO_LANES,
                           MX_EINVAL; same results                            */

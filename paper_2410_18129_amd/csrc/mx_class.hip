@@ -98,7 +98,7 @@ constexpr int kRW = words_for(28 * kN);                   // Montgomery-domain v
 static_assert(!kHasBlk || (kK >= 1 && kK <= 4), "block kernels: redundant limbs need K <= 4");
 // block exponentiations of at most this many instances run four (two) lanes
 // per instance: 65536 lanes = one wavefront on each of MI355X's 1024 SIMDs
-constexpr uint32_t kFourLaneMax = 16384;
+constexpr uint32_t kFourLaneMax = 32768;  // four lanes (arrays in LDS) beat one and two up to here
 constexpr uint32_t kTwoLaneMax = 32768;
 
 // k_modexp with a register budget for two wavefronts per SIMD: at 1024 bits the
@@ -281,10 +281,10 @@ hipError_t modexp_fn(int impl, int redc, const CtxDev& ctx, const uint32_t* cidx
   }
   if constexpr (kBlock || kHasBlk) {
     if (kBlock || impl == 1 || impl == 3 || impl == 4 || impl == 5) {
-      // a batch that leaves SIMDs without a wavefront runs four or two lanes per
-      // instance (lower latency, more lanes) unless one lane (impl 3) or at most two
-      // (impl 4) were asked for; four at any size when asked for (impl 5); the
-      // workspace has room for any of them
+      // a batch of at most two wavefronts per SIMD at four lanes runs four lanes per
+      // instance (lower latency, and faster than one or two lanes at these sizes)
+      // unless one lane (impl 3) or at most two (impl 4) were asked for; four at any
+      // size when asked for (impl 5); the workspace has room for any of them
       if ((count <= kFourLaneMax && impl != 3 && impl != 4) || impl == 5) {
         const uint32_t blocks4 = (count + 15) / 16;
         if (trunc)

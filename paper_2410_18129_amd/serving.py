@@ -210,11 +210,11 @@ class GpuExecutor:
     """
 
     def __init__(self, trace, max_batch, mem_budget, windows=None, max_slots=4, device="cuda", one_lane_from=16384,
-                 two_lanes_from=4096):
+                 two_lanes_from=None):
         import torch
         self.torch = torch
         self.one_lane_from = one_lane_from
-        self.two_lanes_from = two_lanes_from
+        self.two_lanes_from = one_lane_from if two_lanes_from is None else two_lanes_from
         self.classes = trace.classes
         self.ctx = {c: mx.Context(trace.mods[c], c) for c in self.classes}
         self.windows = windows or {c: 0 for c in self.classes}
@@ -247,8 +247,9 @@ class GpuExecutor:
         torch = self.torch
         st = slot["stream"]
         # the batch size tells the load: the block kernels keep one lane per instance for
-        # large batches (throughput), at most two for middle-sized ones, and run four lanes per
-        # instance for small ones (latency of a lightly loaded device)
+        # large batches (throughput: the other classes' work fills the SIMDs one lane leaves
+        # idle) and run four lanes per instance below (latency); two lanes only when asked for
+        # (two_lanes_from), four lanes being faster than two at every batch size
         n = hi - lo
         mx.modexp_ws(self.ctx[c], self.base[c][lo:hi], self.exp[c][lo:hi], c, slot["ws"], window=self.windows[c],
                      out=self.out[c][lo:hi], ctx_idx=self.cidx[c][lo:hi], stream=st,

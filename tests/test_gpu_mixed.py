@@ -64,9 +64,9 @@ def test_block_kernel_small_and_large_windows(mx, window):
 
 
 def test_block_kernel_one_two_and_four_lanes_per_instance_agree(mx):
-    # batches of at most 16384 instances run four lanes per instance, up to 32768 two, larger ones
-    # one: the same instances computed all three ways (a 33001-instance batch, a 20001-instance and
-    # a 4001-instance slice of it) and with one lane forced
+    # batches of at most 32768 instances run four lanes per instance, larger ones one: the same
+    # instances computed by a 33001-instance batch (one lane) and by a 20001-instance and a
+    # 4001-instance slice of it (four lanes), then with one, two and four lanes forced
     bits, n = 1024, 33001
     mods = wl.random_moduli(wl.stream(13, "moduli"), bits, n)
     ctx = mx.Context(mods, bits)
@@ -77,22 +77,21 @@ def test_block_kernel_one_two_and_four_lanes_per_instance_agree(mx):
     import torch
     lo, hi = 29000, 33001
     idx = torch.arange(lo, hi, dtype=torch.int32, device=bd.device)
-    two = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
-                             ctx_idx=idx))
-    assert two == one[lo:hi]  # four lanes per instance
+    four = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
+                              ctx_idx=idx))
+    assert four == one[lo:hi]  # four lanes per instance
     lo2 = n - 20001
     idx2 = torch.arange(lo2, n, dtype=torch.int32, device=bd.device)
     assert dev_ints(mx.modexp(ctx, bd[lo2:].contiguous(), ed[lo2:].contiguous(), bits, window=3, block=True,
-                              ctx_idx=idx2)) == one[lo2:]  # two lanes per instance
+                              ctx_idx=idx2)) == one[lo2:]  # four lanes per instance
     forced = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
                                 ctx_idx=idx, one_lane=True))  # MX_ONE_LANE: one lane per instance at any size
     assert forced == one[lo:hi]
-    capped = dev_ints(mx.modexp(ctx, bd[lo:hi].contiguous(), ed[lo:hi].contiguous(), bits, window=3, block=True,
-                                ctx_idx=idx, two_lanes=True))  # MX_TWO_LANES: two lanes where four would run
-    assert capped == one[lo:hi]
-    four = dev_ints(mx.modexp(ctx, bd[lo2:].contiguous(), ed[lo2:].contiguous(), bits, window=3, block=True,
-                              ctx_idx=idx2, four_lanes=True))  # MX_FOUR_LANES: four lanes where two would run
-    assert four == one[lo2:]
+    capped = dev_ints(mx.modexp(ctx, bd[lo2:].contiguous(), ed[lo2:].contiguous(), bits, window=3, block=True,
+                                ctx_idx=idx2, two_lanes=True))  # MX_TWO_LANES: two lanes where four would run
+    assert capped == one[lo2:]
+    big = dev_ints(mx.modexp(ctx, bd, ed, bits, window=3, block=True, four_lanes=True))  # MX_FOUR_LANES at 33001
+    assert big == one
     M, Bs, Es = wl.words_to_ints(mods), wl.words_to_ints(base), wl.words_to_ints(exps)
     for i in (0, 32767, 32768, n - 1):
         assert one[i] == oracle.modexp(Bs[i], Es[i], M[i], bits)
