@@ -1,4 +1,5 @@
-// Block-level schoolbook for the large size classes (3072 and 4096 bits).
+// Block-level kernels for the large size classes (3072 and 4096 bits; 1024 and 2048 bits as well, for
+// comparison and for small batches).
 //
 // A number of n = K H limbs is K blocks of H = 37 limbs.  Every phase of the
 // Montgomery product is a loop over block pairs (i, j), each pair handled by
@@ -12,14 +13,18 @@
 //             above the anti-diagonal, the columns >= H - 2 of the
 //             anti-diagonal products, and the single top partial product of
 //             the pairs i + j = K - 2 (global column n - 2); plain: all pairs.
-// Block results are added into redundant 32-bit limbs (each limb stays below
-// 2^32 for K <= 4) in a per-lane workspace and normalised once per phase.
-// The truncated result uses the same two-column ceil correction as redc():
-// with S the exact sum of the known columns n-2 .. 2n-1,
-// C = floor(S / 2^56) + [S mod 2^56 != 0].
+// The pairs of one diagonal add into 64-bit column sums held in registers,
+// and each block of columns is normalised once, when it is final (block
+// product scanning, below).  The truncated result uses the same two-column
+// ceil correction as redc(): with S the exact sum of the known columns
+// n-2 .. 2n-1, C = floor(S / 2^56) + [S mod 2^56 != 0].  Also here: the
+// block Karatsuba product (Section 3; redundant 32-bit limbs in the
+// workspace), the Karatsuba-truncated q N (Section 5) and CIOS with block
+// words (Algorithm 4).
 //
-// One lane per instance.  Every loop bound, branch and workspace address
-// depends only on public values (sizes, step counter, window size).
+// One lane per instance, or two or four (the residue split below; with four
+// the arrays live in LDS).  Every loop bound, branch and address depends
+// only on public values (sizes, step counter, window size, lane index).
 #pragma once
 #include "mx_kernels.hpp"
 
@@ -835,23 +840,24 @@ __device__ __forceinline__ void res_emit(const uint64_t (&cols)[NU], uint64_t& c
 }
 
 // The high columns H .. 2H - 2 become the next diagonal's columns 0 .. H - 2: lane r' takes column
-// LP u' + r' + H from lane (r' + H) mod LP, register u' + (r' + H) / LP; every other register is cleared.
+// LP u' + r' + H from lane s = (r' + H) mod LP, register u' + (r' + H) / LP; every other register is
+// cleared.  The wrap ((r' + H) / LP = q0 + 1) happens exactly when s < H mod LP, so each source lane
+// picks the register it hands over and one rotation moves it.
 template <int H, int LP, int NU>
 __device__ __forceinline__ void res_roll(uint64_t (&cols)[NU], uint32_t r) {
   constexpr int h0 = H % LP, q0 = H / LP;
   constexpr int NUP = (H - 2) / LP + 1;  // registers of the columns 0 .. H - 2
   static_assert(NUP + q0 <= NU, "rolled registers");
-  const bool wrap = r + h0 >= (uint32_t)LP;
+  const bool wraps = r < (uint32_t)h0;  // as a source lane
   uint64_t nx[NUP];
   sfor<0, NUP>([&](auto U) {
     constexpr int u = decltype(U)::value;
-    const uint64_t x0 = grp_read64<LP, h0, true>(cols[u + q0]);
-    if constexpr (u + q0 + 1 < NU) {
-      const uint64_t x1 = grp_read64<LP, h0, true>(cols[u + q0 + 1]);
-      nx[u] = wrap ? x1 : x0;
-    } else {
-      nx[u] = wrap ? 0ull : x0;
-    }
+    uint64_t x;
+    if constexpr (u + q0 + 1 < NU)
+      x = wraps ? cols[u + q0 + 1] : cols[u + q0];
+    else
+      x = wraps ? 0ull : cols[u + q0];
+    nx[u] = grp_read64<LP, h0, true>(x);
   });
   sfor<0, NU>([&](auto U) {
     constexpr int u = decltype(U)::value;
