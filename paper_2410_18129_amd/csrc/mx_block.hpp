@@ -748,7 +748,9 @@ __device__ __forceinline__ uint64_t grp_read64(uint64_t v) {
   constexpr int ctrl = quad_ctrl<LP, S, ROT>();
   const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, ctrl, 0xF, 0xF, false);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), ctrl, 0xF, 0xF, false);
-  return ((uint64_t)hi << 32) | lo;
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  const u32x2 p = {lo, hi};
+  return __builtin_bit_cast(uint64_t, p);
 }
 
 template <int H, int LP>
@@ -833,7 +835,7 @@ template <int H, int LP, int NU>
 __device__ __forceinline__ void res_emit(const uint64_t (&cols)[NU], uint64_t& carry, uint32_t (&o)[H]) {
   sfor<0, H>([&](auto D) {
     constexpr int k = decltype(D)::value;
-    const uint64_t v = grp_read64<LP, k % LP, false>(cols[k / LP] + carry);  // the carry is alike in the group
+    const uint64_t v = grp_read64<LP, k % LP, false>(cols[k / LP]) + carry;
     o[k] = (uint32_t)v & kLimbMask;
     carry = v >> kLimbBits;
   });
