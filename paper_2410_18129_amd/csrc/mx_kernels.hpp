@@ -109,6 +109,9 @@ __global__ void __launch_bounds__(64) k_ctx_init(const uint64_t* __restrict__ mo
 }
 
 // ---- batched modmul / modsqr ---------------------------------------------
+// A word in LDS named by its address space (3), so that reads of it are ds_read.
+typedef __attribute__((address_space(3))) uint32_t LdsU32;
+
 // out = REDC(a * b) (or REDC(a^2)) for each instance, values of RW words.
 template <int N, int RW, bool TRUNC, bool SQR>
 __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restrict__ cidx,
@@ -138,10 +141,10 @@ __global__ void __launch_bounds__(64) k_mont(CtxDev ctx, const uint32_t* __restr
     mul_sb<N, RotMad>(x, y, t);
   }
   uint32_t r[N];
-  // volatile reads: in this straight-line kernel the compiler would otherwise
-  // hoist every N and N' read to the staging point (the compiler barriers
-  // between column blocks do not order LDS reads) and spill them
-  const volatile uint32_t* sm = s_ctx + threadIdx.x;
+  // N and N' are read through a pointer in the LDS address space: through a
+  // generic pointer the reads are flat loads (the vector memory path, 64-bit
+  // addresses that spilled), and volatile reads would wait for each read
+  const LdsU32* sm = (const LdsU32*)(s_ctx + threadIdx.x);
   redc_blk<N, TRUNC, RotMad>(t, [&](int i) { return sm[i * 64]; }, [&](int i) { return sm[(N + i) * 64]; }, r);
   if (live) contract<N, RW>(r, out + (size_t)inst * RW);
 }

@@ -31,8 +31,7 @@ __global__ void __launch_bounds__(64) k_mont_kredc(CtxDev ctx, const uint32_t* _
     expand<N, RW>(b + (size_t)inst * RW, y);
     mul_sb<N, RotMad>(x, y, t);
   }
-  // volatile reads keep each LDS read next to its use (as in k_mont)
-  const volatile uint32_t* sm = s_ctx + threadIdx.x;
+  const LdsU32* sm = (const LdsU32*)(s_ctx + threadIdx.x);  // ds_read, as in k_mont
   uint32_t q[N], r[N];
   low_half_q<N, RotMad>(t, [&](int i) { return sm[(N + i) * 64]; }, q);
   kara_high_half<N, RotMad>(t, q, [&](int j) { return sm[j * 64]; }, r);
