@@ -53,6 +53,12 @@ struct LaneBuf {
   __device__ __forceinline__ void st(uint32_t row, uint32_t v) const { bstore(r, v, vo, row * ls); }
   __device__ __forceinline__ uint32_t ldx(uint32_t row, uint32_t x) const { return bload(r, vo + x * ls, row * ls); }
   __device__ __forceinline__ void stx(uint32_t row, uint32_t x, uint32_t v) const { bstore(r, v, vo + x * ls, row * ls); }
+  // a read marked non-temporal (cache-policy bit NT): the table scan streams the whole table every window, and
+  // L2 lines it fills this way go first, so that N and N', read from the context arrays, stay
+  __device__ __forceinline__ uint32_t ldx_stream(uint32_t row, uint32_t x) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)(vo + x * ls), (int)(row * ls), kPolicyNT);
+  }
+  static constexpr int kPolicyNT = 2;
 };
 
 // The same view of an array in LDS: p is this lane's word of row 0, ls words between rows.
@@ -1391,10 +1397,10 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
               constexpr uint32_t i = decltype(I)::value;
               const uint32_t l = SP * (t0 + i) + rs;  // this lane's limb
               if constexpr (kFull) {
-                g[u][i] = ws.ldx(er, l);
+                g[u][i] = ws.ldx_stream(er, l);
               } else {  // past n: row n - 1 under a zero mask
                 const bool li = l < n;
-                g[u][i] = ws.ldx(er, li ? l : n - 1u) & (li ? 0xFFFFFFFFu : 0u);
+                g[u][i] = ws.ldx_stream(er, li ? l : n - 1u) & (li ? 0xFFFFFFFFu : 0u);
               }
             });
           });
