@@ -53,12 +53,12 @@ struct LaneBuf {
   __device__ __forceinline__ void st(uint32_t row, uint32_t v) const { bstore(r, v, vo, row * ls); }
   __device__ __forceinline__ uint32_t ldx(uint32_t row, uint32_t x) const { return bload(r, vo + x * ls, row * ls); }
   __device__ __forceinline__ void stx(uint32_t row, uint32_t x, uint32_t v) const { bstore(r, v, vo + x * ls, row * ls); }
-  // a read marked non-temporal (cache-policy bit NT): the table scan streams the whole table every window, and
-  // L2 lines it fills this way go first, so that N and N', read from the context arrays, stay
-  __device__ __forceinline__ uint32_t ldx_stream(uint32_t row, uint32_t x) const {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)(vo + x * ls), (int)(row * ls), kPolicyNT);
+  // a read with cache policy P (kPolicyNT for the scan of tables the caches cannot hold, stream_tables):
+  // L2 lines filled that way go first, so that N and N', read from the context arrays, stay
+  template <int P>
+  __device__ __forceinline__ uint32_t ldx_pol(uint32_t row, uint32_t x) const {
+    return bload_pol<P>(r, vo + x * ls, row * ls);
   }
-  static constexpr int kPolicyNT = 2;
 };
 
 // The same view of an array in LDS: p is this lane's word of row 0, ls words between rows.
@@ -1337,6 +1337,7 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
   const uint64_t* e64 = ex + (size_t)inst * ewords;
 
   const uint32_t nent = 1u << w;
+  const bool stream = stream_tables(count, nent, (uint32_t)n * 4u);
   const uint32_t nwin = ebits ? (ebits + w - 1) / w : 1u;
   // G[0] = R mod N
   copy_rows_split<SP, n>(ws, Lay::G, cr1, 0, rs);
@@ -1384,33 +1385,41 @@ __device__ __forceinline__ void modexp_tile_blk(const CtxDev& ctx, const uint32_
       for (uint32_t t0 = 0; t0 < NT; t0 += CH) {
         uint32_t acc[CH];
         sfor<0, CH>([&](auto I) { acc[decltype(I)::value] = 0; });
+        // the reads' cache policy (a uniform choice from the launch's size) selects one of two loop copies
+        auto scan = [&](auto pol) {
+          constexpr int P = decltype(pol)::value;
 #pragma nounroll
-        for (uint32_t e = 0; e < nent; e += SE) {
-          uint32_t g[SE][CH];
-          uint32_t mask[SE];
-          sfor<0, SE>([&](auto U) {
-            constexpr uint32_t u = decltype(U)::value;
-            const bool in = e + u < nent;
-            mask[u] = in && e + u == bits ? 0xFFFFFFFFu : 0u;
-            const uint32_t er = Lay::G + (in ? e + u : 0u) * n;
-            sfor<0, CH>([&](auto I) {
-              constexpr uint32_t i = decltype(I)::value;
-              const uint32_t l = SP * (t0 + i) + rs;  // this lane's limb
-              if constexpr (kFull) {
-                g[u][i] = ws.ldx_stream(er, l);
-              } else {  // past n: row n - 1 under a zero mask
-                const bool li = l < n;
-                g[u][i] = ws.ldx_stream(er, li ? l : n - 1u) & (li ? 0xFFFFFFFFu : 0u);
-              }
+          for (uint32_t e = 0; e < nent; e += SE) {
+            uint32_t g[SE][CH];
+            uint32_t mask[SE];
+            sfor<0, SE>([&](auto U) {
+              constexpr uint32_t u = decltype(U)::value;
+              const bool in = e + u < nent;
+              mask[u] = in && e + u == bits ? 0xFFFFFFFFu : 0u;
+              const uint32_t er = Lay::G + (in ? e + u : 0u) * n;
+              sfor<0, CH>([&](auto I) {
+                constexpr uint32_t i = decltype(I)::value;
+                const uint32_t l = SP * (t0 + i) + rs;  // this lane's limb
+                if constexpr (kFull) {
+                  g[u][i] = ws.template ldx_pol<P>(er, l);
+                } else {  // past n: row n - 1 under a zero mask
+                  const bool li = l < n;
+                  g[u][i] = ws.template ldx_pol<P>(er, li ? l : n - 1u) & (li ? 0xFFFFFFFFu : 0u);
+                }
+              });
             });
-          });
-          sfor<0, CH>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            uint32_t v = acc[i];
-            sfor<0, SE>([&](auto U) { v |= g[decltype(U)::value][i] & mask[decltype(U)::value]; });
-            acc[i] = v;
-          });
-        }
+            sfor<0, CH>([&](auto I) {
+              constexpr int i = decltype(I)::value;
+              uint32_t v = acc[i];
+              sfor<0, SE>([&](auto U) { v |= g[decltype(U)::value][i] & mask[decltype(U)::value]; });
+              acc[i] = v;
+            });
+          }
+        };
+        if (stream)
+          scan(std::integral_constant<int, kPolicyNT>{});
+        else
+          scan(std::integral_constant<int, 0>{});
         sfor<0, CH>([&](auto I) {
           constexpr uint32_t i = decltype(I)::value;
           const uint32_t l = SP * (t0 + i) + rs;

@@ -23,6 +23,19 @@ __device__ __forceinline__ uint32_t bload(__amdgpu_buffer_rsrc_t r, uint32_t vof
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t voff, uint32_t soff) {
   __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, 0);
 }
+// Cache policy of the constant-time table scan's reads.  Every window streams the whole table of every
+// instance; when the launch's tables exceed the 256 MB last-level cache no cache level can keep them, and the
+// scan reads them with the non-temporal policy (bit NT of the buffer instruction's cache-policy field), which
+// leaves the caches to the rest of the kernel's traffic.  Tables that fit are read with the default policy.
+constexpr int kPolicyNT = 2;
+constexpr uint64_t kCacheBytes = 256ull << 20;
+__device__ __forceinline__ bool stream_tables(uint32_t count, uint32_t nent, uint32_t entry_bytes) {
+  return (uint64_t)count * nent * entry_bytes > kCacheBytes;
+}
+template <int P>
+__device__ __forceinline__ uint32_t bload_pol(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, P);
+}
 
 // Copies this lane's N and N' limbs into its LDS column ([limb][lane]).  Each
 // lane reads back only its own column, so no barrier is needed.  The reads of
@@ -253,6 +266,7 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
   const uint64_t* e64 = ex + (size_t)inst * ewords;
 
   const uint32_t nent = 1u << w;
+  const bool stream = stream_tables(count, nent, (uint32_t)packed_words(N) * 4u);
   const uint32_t nwin = ebits ? (ebits + w - 1) / w : 1u;
 
   uint32_t n0 = 0;
@@ -315,23 +329,31 @@ __device__ __forceinline__ void modexp_tile(const CtxDev& ctx, const uint32_t* _
       // full masked scan: every entry is read, the selected one survives
       uint32_t selw[NW];
       sfor<0, NW>([&](auto I) { selw[decltype(I)::value] = 0; });
-      // two entries per iteration keep 2 NW loads in flight (nent >= 2)
+      // two entries per iteration keep 2 NW loads in flight (nent >= 2); the policy (a uniform choice from
+      // the launch's size) selects one of two copies of the loop
+      auto scan = [&](auto pol) {
+        constexpr int P = decltype(pol)::value;
 #pragma nounroll
-      for (uint32_t e = 0; e < nent; e += 2) {
-        const uint32_t mask0 = e == bits ? 0xFFFFFFFFu : 0u;
-        const uint32_t mask1 = e + 1 == bits ? 0xFFFFFFFFu : 0u;
-        const uint32_t s0 = e * ent_bytes;
-        uint32_t v0[NW], v1[NW];
-        sfor<0, NW>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          v0[i] = bload(tr, tvo, s0 + (uint32_t)i * tls);
-          v1[i] = bload(tr, tvo, s0 + ent_bytes + (uint32_t)i * tls);
-        });
-        sfor<0, NW>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          selw[i] |= (v0[i] & mask0) | (v1[i] & mask1);
-        });
-      }
+        for (uint32_t e = 0; e < nent; e += 2) {
+          const uint32_t mask0 = e == bits ? 0xFFFFFFFFu : 0u;
+          const uint32_t mask1 = e + 1 == bits ? 0xFFFFFFFFu : 0u;
+          const uint32_t s0 = e * ent_bytes;
+          uint32_t v0[NW], v1[NW];
+          sfor<0, NW>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            v0[i] = bload_pol<P>(tr, tvo, s0 + (uint32_t)i * tls);
+            v1[i] = bload_pol<P>(tr, tvo, s0 + ent_bytes + (uint32_t)i * tls);
+          });
+          sfor<0, NW>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            selw[i] |= (v0[i] & mask0) | (v1[i] & mask1);
+          });
+        }
+      };
+      if (stream)
+        scan(std::integral_constant<int, kPolicyNT>{});
+      else
+        scan(std::integral_constant<int, 0>{});
       unpack<N>(selw, bsrc);
       if (kind == kLoadSel) {
         sfor<0, N>([&](auto I) { y[decltype(I)::value] = bsrc[decltype(I)::value]; });
